@@ -382,29 +382,55 @@ def sphere_apr(cfg: SphereConfig, return_image: bool = False):
     return out
 
 
+def cells_from_access(dims, l_min, l_max, y_idx, xz_end) -> Dict[int, np.ndarray]:
+    """Per-level (z, x, y) cell lists of a LinearAccess (inverse of encode_cells)."""
+    cells = {}
+    row0 = 0
+    ends = np.asarray(xz_end, np.int64)
+    for l in range(l_min, l_max + 1):
+        dz, dx, _ = level_dims(dims, l_max, l)
+        nrow = dz * dx
+        e = ends[row0:row0 + nrow]
+        b = np.concatenate([[ends[row0 - 1] if row0 > 0 else 0], e[:-1]])
+        rows = np.repeat(np.arange(nrow, dtype=np.int64), e - b)
+        p0 = int(ends[row0 - 1]) if row0 > 0 else 0
+        ys = np.asarray(y_idx[p0:p0 + rows.size], np.int32)
+        cells[l] = np.stack([(rows // dx).astype(np.int32), (rows % dx).astype(np.int32), ys], axis=1)
+        row0 += nrow
+    return cells
+
+
 def cached_sphere_apr(name: str, cache_dir: Optional[str] = None) -> AprInput:
-    """``sphere_apr(CONFIGS[name])`` memoised as an .npz file."""
+    """``sphere_apr(CONFIGS[name])`` memoised as an .npz file (y_idx, xz_end,
+    values; the cell lists are rebuilt from them)."""
+    import hashlib
     import os
     cfg = CONFIGS[name]
     if cache_dir is None:
         cache_dir = os.environ.get("APRGEN_CACHE",
                                    os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "_cache"))
     os.makedirs(cache_dir, exist_ok=True)
-    import hashlib
     key = hashlib.sha1(repr(dataclasses.astuple(cfg)).encode()).hexdigest()[:10]
     path = os.path.join(cache_dir, f"{name}_{key}.npz")
     l_max = lmax_for(cfg.dims)
     if os.path.exists(path):
         z = np.load(path, allow_pickle=False)
-        cells = {l: z[f"cells_{l}"] for l in range(cfg.l_min, l_max + 1)}
-        return AprInput(tuple(cfg.dims), cfg.l_min, l_max, cells, z["values"], z["y_idx"],
-                        z["xz_end"], meta={"kind": "sphere", "name": name,
-                                           "n_particles": int(z["values"].shape[0]),
-                                           "cr": float(np.prod(cfg.dims)) / max(1, z["values"].shape[0])})
+        y_idx, xz_end, values = z["y_idx"], z["xz_end"], z["values"]
+        cells = cells_from_access(cfg.dims, cfg.l_min, l_max, y_idx, xz_end)
+        return AprInput(tuple(cfg.dims), cfg.l_min, l_max, cells, values, y_idx, xz_end,
+                        meta={"kind": "sphere", "name": name, "n_particles": int(values.shape[0]),
+                              "cr": float(np.prod(cfg.dims)) / max(1, values.shape[0])})
     a = sphere_apr(cfg)
-    tmp = path + ".tmp.npz"
-    np.savez(tmp, values=a.values, y_idx=a.y_idx, xz_end=a.xz_end,
-             **{f"cells_{l}": a.cells[l] for l in a.cells})
+    tmp = path + f".{os.getpid()}.tmp.npz"
+    np.savez(tmp, values=a.values, y_idx=a.y_idx, xz_end=a.xz_end)
     os.replace(tmp, path)
     a.meta["name"] = name
     return a
+
+
+def gaussian_stencil(k: int, sigma: float) -> np.ndarray:
+    """Normalised separable Gaussian filter [k, k, k] (FP64), a filter input."""
+    t = np.arange(k) - (k - 1) / 2.0
+    g = np.exp(-0.5 * (t / sigma) ** 2)
+    g = g / g.sum()
+    return np.einsum("i,j,k->ijk", g, g, g)

@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of APR-native convolution on one MI355X.
+
+One step = tree fill + 3^3 APR convolution + 5^3 APR convolution of the same
+particle values (the tree is shared by both filters), FP32, on the 512^3
+sphere-field APR (~6.6M particles, pixels/particles ~20).  Inputs are resident
+in device memory before timing starts; the access structure (tree structure
+and tile list) is built once, outside the timed region.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gparticles/s + pixel-equiv GB/s (3³/5³ APR conv); surrogate-vs-plain RL speedup"
+HBM_PEAK_GBPS = 8000.0
+# FP32 vector FMA without packed math (the library is built with packed FP32
+# disabled): 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def source_hash() -> str:
+    h = hashlib.sha1()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2112_03592_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def conv_bytes(n_p, n_t, rows, trows, bv=4):
+    """Compulsory bytes of one convolution: particle values + y, tree values +
+    y, row ends (each read once), outputs written once."""
+    return n_p * (bv + 2 + bv) + n_t * (bv + 2) + 4 * (rows + trows)
+
+
+def fill_bytes(n_p, n_t, rows, trows, bv=4):
+    """Tree fill: particle values + y read, tree y read, tree values written
+    and read back once as children of the next coarser level."""
+    return n_p * (bv + 2) + n_t * (2 + bv + bv) + 4 * (rows + trows)
+
+
+def cpu_baseline(inp, sample: int):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import access as A
+    from oracle import conv as C
+    from oracle import stencil as S
+    from oracle.tree import fill_tree
+    with threadpool_limits(1):
+        la = A.LinearAccess(inp.dims, inp.l_min, inp.l_max, inp.y_idx, inp.xz_end)
+        tr = A.tree_structure(la)
+        x = inp.values.astype(np.float64)
+        t0 = time.perf_counter()
+        tv = fill_tree(la, tr, x)
+        t_fill = time.perf_counter() - t0
+        smp = np.sort(np.random.default_rng(0).choice(la.n, sample, replace=False))
+        t_conv = 0.0
+        for k in (3, 5):
+            w = S.level_stencils(S.gaussian_stencil(k, 1.0), S.SAME, la.l_min, la.l_max)
+            t0 = time.perf_counter()
+            C.apr_conv_keyed(la, x, w, smp, tree=tr, tvals=tv)
+            t_conv += time.perf_counter() - t0
+    step = t_fill + t_conv * la.n / sample
+    return {"value": la.n / step / 1e9, "unit": "Gparticles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle, 1 thread: full tree fill ({t_fill:.2f} s) + keyed 3^3 and 5^3 "
+                       f"convolution of {sample} seeded particles ({t_conv:.2f} s), extrapolated to "
+                       f"all {la.n} particles; estimated step {step:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sphere512")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 15)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(multi-GPU sharding of the APR is a design in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from aprgen.apr_input import CONFIGS, cached_sphere_apr
+    from paper_2112_03592_amd import apr as G
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    log(f"workload {args.workload}: generating / loading input")
+    inp = cached_sphere_apr(args.workload)
+    cfg = CONFIGS[args.workload]
+    n_p = inp.n_particles
+    n_px = int(np.prod(inp.dims))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = G.AprAccess.from_input(inp)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    log(f"access built: N_p={n_p} N_t={acc.n_tree} tiles={acc.n_tiles} ({build_ms:.1f} ms)")
+
+    x = torch.from_numpy(inp.values).cuda()
+    tree = torch.empty(acc.n_tree, dtype=torch.float32, device="cuda")
+    y3 = torch.empty(n_p, dtype=torch.float32, device="cuda")
+    y5 = torch.empty(n_p, dtype=torch.float32, device="cuda")
+    from aprgen.apr_input import gaussian_stencil
+    w = {k: torch.from_numpy(G.stencil_levels(gaussian_stencil(k, 1.0), "same", k, inp.l_min,
+                                              inp.l_max)).cuda() for k in (3, 5)}
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        G.fill_tree(acc, x, tree)
+        if ev is not None:
+            ev[1].record()
+        G.conv(acc, x, tree, w[3], 3, y=y3)
+        if ev is not None:
+            ev[2].record()
+        G.conv(acc, x, tree, w[5], 5, y=y5)
+        if ev is not None:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    start.record()
+    for i in range(args.steps):
+        step(evs[i])
+    stop.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - w0) * 1e3
+    ms_per_step = start.elapsed_time(stop) / args.steps
+    fill_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    c3_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    c5_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    log(f"step {ms_per_step:.3f} ms (wall {wall_ms / args.steps:.3f} ms): fill {fill_ms:.3f} "
+        f"conv3 {c3_ms:.3f} conv5 {c5_ms:.3f}")
+
+    rows, trows, n_t = acc.n_rows, acc.n_tree_rows, acc.n_tree
+    kern = {"fill": (fill_ms, fill_bytes(n_p, n_t, rows, trows), 8 * n_t),
+            "conv3": (c3_ms, conv_bytes(n_p, n_t, rows, trows), 2 * 27 * n_p),
+            "conv5": (c5_ms, conv_bytes(n_p, n_t, rows, trows), 2 * 125 * n_p)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    t_ms, bytes_alg, flops = kern[dom]
+    t_hbm = bytes_alg / (HBM_PEAK_GBPS * 1e9)
+    t_alu = flops / (FP32_VALU_PEAK_TFLOPS * 1e12)
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tj = json.load(f)
+        ent = tj.get("kernels", {}).get(dom)
+        if ent and tj.get("source_sha") == source_hash() and tj.get("workload") == args.workload:
+            traffic = ent["hbm_bytes_per_launch"]
+    if t_hbm >= t_alu:
+        achieved = bytes_alg / (t_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic}
+    else:
+        achieved = flops / (t_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic}
+    roof.update({"kernel": dom, "launch_ms": t_ms, "algorithmic_bytes": bytes_alg,
+                 "algorithmic_flops": flops})
+
+    def rate(ms):
+        return {"ms": ms, "Gparticles_s": n_p / (ms * 1e-3) / 1e9,
+                "pixel_equiv_GBps": n_px * 4 / (ms * 1e-3) / 1e9}
+
+    value = n_p / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "Gparticles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{args.workload}: {inp.dims[0]}x{inp.dims[1]}x{inp.dims[2]} sphere field, "
+                                f"{cfg.n_spheres} spheres r {cfg.r_min:g}-{cfg.r_max:g}, levels "
+                                f"{inp.l_min}-{inp.l_max}; step = tree fill + 3^3 + 5^3 Gaussian (sigma 1) "
+                                f"APR convolution, same stencil at every level"),
+                   "n_particles": n_p, "n_tree": n_t, "pixels_per_particle": n_px / n_p,
+                   "tiles": acc.n_tiles},
+        "pixel_equiv_GBps": n_px * 4 / (ms_per_step * 1e-3) / 1e9,
+        "stages_ms": {"fill": fill_ms, "conv3": c3_ms, "conv5": c5_ms, "access_build_once": build_ms},
+        "pipeline_3x3x3": rate(fill_ms + c3_ms),
+        "pipeline_5x5x5": rate(fill_ms + c5_ms),
+        "roofline": roof,
+        "source_sha": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on a {args.cpu_sample}-particle sample")
+        out["cpu_baseline"] = cpu_baseline(inp, args.cpu_sample)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * aprconv.h -- C ABI of the MI355X (gfx950) library for discrete convolution
+ * computed directly on an Adaptive Particle Representation (APR) of an image.
+ *
+ * Paper: "Parallel Discrete Convolutions on Adaptive Particle Representations
+ * of Images" (Jonsson, Cheeseman, Maddu, Gonciarz, Sbalzarini; arXiv
+ * 2112.03592).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an apr_status.  On failure nothing has been
+ *   launched and apr_last_error() returns a message for the calling thread.
+ *   No C++ exception crosses this boundary.
+ * - Axes are (z, x, y) with y contiguous (Section 3.1, footnote).  Levels are
+ *   l in [l_min, l_max]; l_max = ceil(log2(max image edge)) (Section 2.1) and
+ *   the grid at level l is ceil(N / 2^(l_max - l)) cells per axis.
+ * - "device" pointers are HIP device memory owned by the caller unless stated
+ *   otherwise; "host" pointers are ordinary host memory.  `stream` is a
+ *   hipStream_t (NULL = the null stream).  Launches are asynchronous on that
+ *   stream unless a function says it synchronizes.
+ * - Particle values are stored as [N_p][C] (channel fastest); tree values as
+ *   [N_t][C]; per-level weights as [n_wlevels][C_out][C_in][k][k][k] with the
+ *   last three axes (dz, dx, dy) + r, r = (k-1)/2, in FP32.
+ * - The library computes cross-correlation: out(c) = sum_o w[o] * V(c + o).
+ *   Convolution in the sense of the paper equals correlation with the
+ *   flipped stencil (apr_stencil_levels can flip).
+ */
+#ifndef APRCONV_H
+#define APRCONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t apr_status;
+#define APR_OK 0
+#define APR_EINVAL 1        /* bad pointer, size, order or argument value */
+#define APR_EUNBALANCED 2   /* neighbouring particle levels differ by > 1 */
+#define APR_EPARTITION 3    /* particle cells overlap or leave a gap */
+#define APR_EUNSUPPORTED 4  /* valid request this build does not handle */
+#define APR_ENOMEM 5        /* device allocation failed */
+#define APR_EDEVICE 6       /* a HIP call failed; message holds its text */
+
+/* storage types of particle / tree values */
+#define APR_F32 0
+#define APR_BF16 1
+
+/* apr_access_desc.flags */
+#define APR_VALIDATE_PARTITION 1u  /* check on the device that the cells partition the image */
+#define APR_VALIDATE_BALANCE 2u    /* check 26-neighbour 2:1 level balance */
+
+#define APR_MAX_LEVELS 17          /* levels 0..16 (y_dim <= 65535) */
+
+/* ----------------------------------------------------------------------
+ * Access structure (Algorithm 1, "LinearAccess") and APR tree (Section 3.4)
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t dims[3];          /* image size in pixels (N_z, N_x, N_y); N_y <= 65535 */
+  int32_t l_min;            /* coarsest particle level, 0 <= l_min <= l_max */
+  int32_t l_max;            /* must equal ceil(log2(max(dims))) */
+  const uint16_t* y_idx;    /* host [n_particles]: y of each particle, order l->z->x->y */
+  int64_t n_particles;      /* < 2^32 - 1 */
+  const uint64_t* xz_end;   /* host [n_rows]: inclusive prefix count of particles per
+                               row; row = level_offset[l] + z * x_dim[l] + x for
+                               l = l_min..l_max; the row begins at xz_end[row-1]
+                               (0 for row 0) */
+  int64_t n_rows;           /* sum over levels of z_dim[l] * x_dim[l] */
+  uint32_t flags;           /* APR_VALIDATE_* */
+} apr_access_desc;
+
+typedef struct {
+  int64_t n_particles, n_tree;           /* N_p, N_t */
+  int64_t n_rows, n_tree_rows;
+  int32_t l_min, l_max, tree_l_min, tree_l_max;  /* tree levels [max(l_min-1,0), l_max-1] */
+  int32_t dims[APR_MAX_LEVELS][3];       /* grid size per level (z, x, y) */
+  int64_t particles_per_level[APR_MAX_LEVELS];
+  int64_t tree_per_level[APR_MAX_LEVELS];
+  int64_t n_tiles;                       /* non-empty convolution tiles, all levels */
+  int64_t device_bytes;                  /* device memory held by the handle */
+} apr_access_info;
+
+typedef struct apr_handle apr_handle;
+
+/* Build the device-side access structure of one APR.
+ * Reads the host arrays in `desc`, validates them (row ends monotone and equal
+ * to n_particles at the end, y strictly increasing within each row and below
+ * the level's y size), copies them to the current HIP device, derives the APR
+ * tree (all interior nodes, Section 3.4: for every tree row the sorted union of
+ * y/2 over the particles and tree nodes of its 2x2 child rows, finest level
+ * first) and the list of non-empty convolution tiles (the non-empty-row
+ * pre-pass of Section 5.2).  Optional device validation per `desc->flags`
+ * returns APR_EPARTITION / APR_EUNBALANCED.  Synchronizes `stream` once before
+ * returning.  The handle owns all its device memory; it is immutable after
+ * the build and may be used from several streams.  Free with
+ * apr_access_destroy. */
+apr_status apr_access_build(const apr_access_desc* desc, void* stream, apr_handle** out);
+
+/* Sizes and counts of a built handle (host struct filled in). */
+apr_status apr_access_get_info(const apr_handle* h, apr_access_info* out);
+
+/* Copy the APR tree's LinearAccess arrays to host memory: tree_y_idx [n_tree]
+ * and tree_xz_end [n_tree_rows] (inclusive ends, rows ordered l->z->x over the
+ * tree levels).  Either pointer may be NULL.  Synchronous. */
+apr_status apr_access_export_tree(const apr_handle* h, uint16_t* tree_y_idx, uint64_t* tree_xz_end);
+
+/* Release the handle and its device memory. NULL is accepted. */
+apr_status apr_access_destroy(apr_handle* h);
+
+/* ----------------------------------------------------------------------
+ * Tree values (Section 3.4, two-step fill)
+ * ---------------------------------------------------------------------- */
+
+/* tree[t][c] = mean over the in-image children c' of node t of V(c'), where
+ * V is the particle value if c' is a particle and the tree value otherwise;
+ * filled from level l_max-1 down to the coarsest tree level.
+ * x: device [N_p][channels], tree: device [N_t][channels], both of `dtype`
+ * (APR_F32 or APR_BF16; FP32 arithmetic).  Deterministic. Asynchronous. */
+apr_status apr_fill_tree(const apr_handle* h, const void* x, void* tree, int32_t channels,
+                         int32_t dtype, void* stream);
+
+/* ----------------------------------------------------------------------
+ * Stencils per level (Section 4.2, Eq. restrict_stenc; Section 4.3,
+ * Eq. adapt_grad)
+ * ---------------------------------------------------------------------- */
+
+#define APR_STENCIL_SAME 0       /* w_l = w */
+#define APR_STENCIL_RESTRICT 1   /* w_l = R_l K_w P_l: average of w applied at every
+                                    position inside the level-l cell */
+#define APR_STENCIL_ADAPTIVE 2   /* w_l = 2^-(l_max-l) w */
+
+/* Host helper, FP64 arithmetic, FP32 output.  w: host [n_filters][k^3]
+ * (n_filters = C_out*C_in); out: host [l_max-l_min+1][n_filters][k^3].
+ * flip != 0 reverses w in every dimension first (the flipped PSF of
+ * Section 6.2).  k in {3, 5}. */
+apr_status apr_stencil_levels(int32_t mode, int32_t k, int32_t n_filters, const double* w,
+                              int32_t l_min, int32_t l_max, int32_t flip, float* out);
+
+/* ----------------------------------------------------------------------
+ * Convolution (Section 4.1; GPU design of Section 5.2)
+ * ---------------------------------------------------------------------- */
+
+#define APR_EPI_NONE 0
+#define APR_EPI_RATIO 1   /* y = u / max(y, eps)   (Richardson-Lucy quotient, Section 6.2) */
+#define APR_EPI_MUL 2     /* y = y * u             (Richardson-Lucy update) */
+
+typedef struct {
+  int32_t k;             /* stencil side: 3 or 5 */
+  int32_t c_in, c_out;   /* channels (this build: 1 and 1) */
+  int32_t n_wlevels;     /* 1 (one stencil for every level) or l_max-l_min+1 */
+  int32_t x_dtype;       /* APR_F32 / APR_BF16: storage of x and tree */
+  int32_t y_dtype;       /* storage of y */
+  int32_t epilogue;      /* APR_EPI_* */
+  float eps;             /* clamp of APR_EPI_RATIO */
+  const void* epi_arg;   /* device [N_p], same dtype as y: u for RATIO and MUL */
+} apr_conv_desc;
+
+/* y[p] = sum_o w_{l_p}[o] * V_{l_p}(c_p + o) for every particle p, with V_l
+ * the level-l reconstruction (Section 3.5): the value of the particle at a
+ * level <= l containing the cell, else the tree value of the cell, 0 outside
+ * the image.  Requires a balanced APR (neighbouring levels differ by <= 1),
+ * so every tap is supplied by APR level l, APR level l-1 or tree level l.
+ * x: device [N_p][c_in]; tree: device [N_t][c_in], filled from this exact x
+ * by apr_fill_tree (not checked); w: device FP32 weights; y: device
+ * [N_p][c_out], must not alias x or tree.  Asynchronous. */
+apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                    const float* w, void* y, void* stream);
+
+/* Test support: for each listed particle and each tap (dz, dx, dy ascending)
+ * write which element supplies V_l(c_p + o), computed by the convolution's own
+ * patch builder: -1 outside the image, else (source << 40) | index with
+ * source 1 = APR level l, 2 = APR level l-1, 3 = tree level l; index is the
+ * global particle or tree index.  particles: device int64 [n] (must be sorted
+ * ascending and unique); out: device int64 [n][k^3].  Asynchronous. */
+apr_status apr_neighbor_map(const apr_handle* h, int32_t k, const int64_t* particles, int64_t n,
+                            int64_t* out, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* apr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APRCONV_H */

@@ -88,6 +88,12 @@ class LinearAccess:
 
     def cells(self, l) -> np.ndarray:
         """(z, x, y) of the level-l particles in storage order, int64 [n_l, 3]."""
+        cache = self.__dict__.setdefault("_cells", {})
+        if l not in cache:
+            cache[l] = self._decode(l)
+        return cache[l]
+
+    def _decode(self, l) -> np.ndarray:
         r0 = self.level_offset[l]
         nrow = self.z_dim[l] * self.x_dim[l]
         ends = self.xz_end[r0:r0 + nrow]
@@ -102,8 +108,11 @@ class LinearAccess:
     def keys(self, l) -> np.ndarray:
         """Linearised cell index (z*x_dim + x)*y_dim + y of the level-l particles;
         sorted ascending because storage order is lexicographic."""
-        c = self.cells(l)
-        return (c[:, 0] * self.x_dim[l] + c[:, 1]) * self.y_dim[l] + c[:, 2]
+        cache = self.__dict__.setdefault("_keys", {})
+        if l not in cache:
+            c = self.cells(l)
+            cache[l] = (c[:, 0] * self.x_dim[l] + c[:, 1]) * self.y_dim[l] + c[:, 2]
+        return cache[l]
 
     def lookup(self, l, cells: np.ndarray) -> np.ndarray:
         """Global index of the element at level l and cell (z,x,y), or -1."""
@@ -155,7 +164,10 @@ def tree_structure(apr: LinearAccess) -> LinearAccess:
             kids.append(nodes[L + 1])
         allk = np.concatenate(kids) if kids else np.zeros((0, 3), np.int64)
         par = allk // 2
-        nodes[L] = np.unique(par, axis=0) if par.shape[0] else par
+        # distinct parents, via their linear index at level L
+        dz, dx, dy = level_dims(apr.dims, apr.dims_lmax, L)
+        key = np.unique((par[:, 0] * dx + par[:, 1]) * dy + par[:, 2])
+        nodes[L] = np.stack([key // (dx * dy), (key // dy) % dx, key % dy], axis=1)
     if t_hi < t_lo:
         return from_cells(apr.dims, t_lo, t_lo - 1, {})
     return from_cells(apr.dims, t_lo, t_hi, nodes)
@@ -168,8 +180,10 @@ def covered_index(apr: LinearAccess, l: int) -> np.ndarray:
     d = level_dims(apr.dims, apr.dims_lmax, l)
     out = np.full(d, -1, np.int64)
     for lq in range(apr.l_min, min(l, apr.l_max) + 1):
+        b, e = apr.level_range(lq)
+        if b == e:
+            continue
         c = apr.cells(lq)
-        b, _ = apr.level_range(lq)
         f = 2 ** (l - lq)
         for a0 in range(f):
             for a1 in range(f):

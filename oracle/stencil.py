@@ -22,6 +22,18 @@ def gaussian_stencil(k: int, sigma: float) -> np.ndarray:
     return g3 / g3.sum()
 
 
+def _axis_counts(s: int, r: int) -> np.ndarray:
+    """n[J + r, t + r] = #{a in [0, s) : floor((a + t) / s) == J}."""
+    n = np.zeros((2 * r + 1, 2 * r + 1))
+    for t in range(-r, r + 1):
+        for a in range(s):
+            J = (a + t) // s
+            if abs(J) > r:
+                raise ValueError("restricted stencil exceeds the stencil support")
+            n[J + r, t + r] += 1
+    return n
+
+
 def restrict_stencil(w: np.ndarray, s: int) -> np.ndarray:
     """Restricted stencil w_l for coarsening factor s (Eq. restrict_stenc).
 
@@ -30,25 +42,41 @@ def restrict_stencil(w: np.ndarray, s: int) -> np.ndarray:
     cell I this reads  s^-3 sum_{a in [0,s)^3} sum_t w[t] u(I + floor((a+t)/s)),
     i.e. (Section 4.2) w_l averages the fine stencil applied at every position
     inside the coarse cell:
-        w_l[J] = s^-3 sum_a sum_t w[t] [floor((a+t)/s) == J].
-    The result is embedded, centred, in the same k^3 support as w (for s >= 2
-    and k <= 5 its non-zeros lie in [-1, 1]^3).  Leading axes are carried.
+        w_l[J] = s^-3 sum_t w[t] #{a in [0,s)^3 : floor((a+t)/s) == J}.
+    The count of positions a is a product of per-axis counts because both the
+    condition and the range of a split over the axes.  The result is embedded,
+    centred, in the same k^3 support as w (for s >= 2 and k <= 5 its non-zeros
+    lie in [-1, 1]^3).  Leading axes are carried.
     """
     w = np.asarray(w, np.float64)
     k = w.shape[-1]
     r = (k - 1) // 2
     if s == 1:
         return w.copy()
+    n = _axis_counts(s, r)
     out = np.zeros_like(w)
-    lead = w.shape[:-3]
+    for t in itertools.product(range(-r, r + 1), repeat=3):
+        wt = w[(...,) + tuple(ti + r for ti in t)]
+        for J in itertools.product(range(-r, r + 1), repeat=3):
+            c = n[J[0] + r, t[0] + r] * n[J[1] + r, t[1] + r] * n[J[2] + r, t[2] + r]
+            if c:
+                out[(...,) + tuple(j + r for j in J)] += wt * (c / s ** 3)
+    return out
+
+
+def restrict_stencil_enumerated(w: np.ndarray, s: int) -> np.ndarray:
+    """The same restriction by enumerating every position a in [0, s)^3
+    (cross-check for small s)."""
+    w = np.asarray(w, np.float64)
+    k = w.shape[-1]
+    r = (k - 1) // 2
+    out = np.zeros_like(w)
     for t in itertools.product(range(-r, r + 1), repeat=3):
         wt = w[(...,) + tuple(ti + r for ti in t)]
         for a in itertools.product(range(s), repeat=3):
             J = tuple((ai + ti) // s for ai, ti in zip(a, t))
-            if any(abs(j) > r for j in J):
-                raise ValueError("restricted stencil exceeds the stencil support")
             out[(...,) + tuple(j + r for j in J)] += wt / s ** 3
-    return out.reshape(lead + (k, k, k))
+    return out
 
 
 def level_stencils(w: np.ndarray, mode: str, l_min: int, l_max: int) -> np.ndarray:

@@ -1,0 +1,88 @@
+"""ctypes declarations of the aprconv C ABI (include/aprconv.h).
+
+Loading fails loudly: there is no fallback implementation of any entry point.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_uint16, c_uint32, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaprconv.so")
+
+APR_OK, APR_EINVAL, APR_EUNBALANCED, APR_EPARTITION, APR_EUNSUPPORTED, APR_ENOMEM, APR_EDEVICE = range(7)
+STATUS_NAMES = {0: "APR_OK", 1: "APR_EINVAL", 2: "APR_EUNBALANCED", 3: "APR_EPARTITION",
+                4: "APR_EUNSUPPORTED", 5: "APR_ENOMEM", 6: "APR_EDEVICE"}
+APR_F32, APR_BF16 = 0, 1
+APR_VALIDATE_PARTITION, APR_VALIDATE_BALANCE = 1, 2
+APR_MAX_LEVELS = 17
+APR_STENCIL_SAME, APR_STENCIL_RESTRICT, APR_STENCIL_ADAPTIVE = 0, 1, 2
+APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL = 0, 1, 2
+
+EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree", "apr_access_destroy",
+            "apr_fill_tree", "apr_stencil_levels", "apr_conv", "apr_neighbor_map", "apr_last_error"]
+
+
+class AccessDesc(ctypes.Structure):
+    _fields_ = [("dims", c_int32 * 3), ("l_min", c_int32), ("l_max", c_int32),
+                ("y_idx", c_void_p), ("n_particles", c_int64), ("xz_end", c_void_p),
+                ("n_rows", c_int64), ("flags", c_uint32)]
+
+
+class AccessInfo(ctypes.Structure):
+    _fields_ = [("n_particles", c_int64), ("n_tree", c_int64), ("n_rows", c_int64),
+                ("n_tree_rows", c_int64), ("l_min", c_int32), ("l_max", c_int32),
+                ("tree_l_min", c_int32), ("tree_l_max", c_int32),
+                ("dims", (c_int32 * 3) * APR_MAX_LEVELS),
+                ("particles_per_level", c_int64 * APR_MAX_LEVELS),
+                ("tree_per_level", c_int64 * APR_MAX_LEVELS),
+                ("n_tiles", c_int64), ("device_bytes", c_int64)]
+
+
+class ConvDesc(ctypes.Structure):
+    _fields_ = [("k", c_int32), ("c_in", c_int32), ("c_out", c_int32), ("n_wlevels", c_int32),
+                ("x_dtype", c_int32), ("y_dtype", c_int32), ("epilogue", c_int32), ("eps", c_float),
+                ("epi_arg", c_void_p)]
+
+
+class AprError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libaprconv.so and declare its signatures (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2112_03592_amd.build` "
+                          f"(the HIP library is required, there is no fallback)")
+    lib = ctypes.CDLL(path)
+    lib.apr_access_build.argtypes = [POINTER(AccessDesc), c_void_p, POINTER(c_void_p)]
+    lib.apr_access_get_info.argtypes = [c_void_p, POINTER(AccessInfo)]
+    lib.apr_access_export_tree.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.apr_access_destroy.argtypes = [c_void_p]
+    lib.apr_fill_tree.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]
+    lib.apr_stencil_levels.argtypes = [c_int32, c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32,
+                                       c_void_p]
+    lib.apr_conv.argtypes = [c_void_p, POINTER(ConvDesc), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.apr_neighbor_map.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_void_p]
+    lib.apr_last_error.argtypes = []
+    lib.apr_last_error.restype = c_char_p
+    for name in EXPORTED:
+        if name != "apr_last_error":
+            getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != APR_OK:
+        msg = load().apr_last_error().decode(errors="replace")
+        raise AprError(status, msg)

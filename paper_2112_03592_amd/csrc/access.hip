@@ -1,0 +1,648 @@
+// Access-structure build: host validation of the particle LinearAccess
+// (Algorithm 1), device derivation of the APR tree (Section 3.4), optional
+// device validation of partition and 2:1 balance, and the non-empty tile
+// list of the convolution (the pre-pass of Section 5.2).
+#include <algorithm>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace apr {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of uint32 (block scan + recursive scan of block sums)
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 4;
+constexpr int kScanBlock = kScanThreads * kScanPerThread;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= uint32_t(o)) v += t;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_block_kernel(uint32_t* data, int64_t n,
+                                                                  uint32_t* sums) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int64_t base = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanPerThread;
+  uint32_t v[kScanPerThread];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPerThread; ++j) {
+    v[j] = (base + j < n) ? data[base + j] : 0u;
+    s += v[j];
+  }
+  uint32_t incl = wave_incl_scan(s);
+  const int w = threadIdx.x / 64;
+  if (lane_id() == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int i = 0; i < w; ++i) woff += wsum[i];
+  uint32_t run = woff + incl - s;
+#pragma unroll
+  for (int j = 0; j < kScanPerThread; ++j) {
+    if (base + j < n) data[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == kScanThreads - 1) {
+    uint32_t tot = 0;
+    for (int i = 0; i < kScanThreads / 64; ++i) tot += wsum[i];
+    sums[blockIdx.x] = tot;
+  }
+}
+
+__global__ void scan_add_kernel(uint32_t* data, int64_t n, const uint32_t* offs) {
+  const int64_t base = int64_t(blockIdx.x) * kScanBlock;
+  const uint32_t o = offs[blockIdx.x];
+  for (int j = threadIdx.x; j < kScanBlock; j += blockDim.x)
+    if (base + j < n) data[base + j] += o;
+}
+
+apr_status scan_u32(uint32_t* data, int64_t n, uint32_t* total_dev, hipStream_t stream) {
+  if (n <= 0) {
+    if (total_dev) APR_HIP(hipMemsetAsync(total_dev, 0, sizeof(uint32_t), stream));
+    return APR_OK;
+  }
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  uint32_t* sums = nullptr;
+  APR_HIP(hipMalloc(&sums, sizeof(uint32_t) * (nb + 1)));
+  hipLaunchKernelGGL(scan_block_kernel, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, data, n,
+                     sums);
+  APR_HIP(hipGetLastError());
+  apr_status st = APR_OK;
+  if (nb > 1) {
+    st = scan_u32(sums, nb, total_dev, stream);
+    if (st == APR_OK) {
+      hipLaunchKernelGGL(scan_add_kernel, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, data,
+                         n, sums);
+      if (hipGetLastError() != hipSuccess) st = APR_EDEVICE;
+    }
+  } else if (total_dev) {
+    if (hipMemcpyAsync(total_dev, sums, sizeof(uint32_t), hipMemcpyDeviceToDevice, stream) !=
+        hipSuccess)
+      st = APR_EDEVICE;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) st = APR_EDEVICE;
+  (void)hipFree(sums);
+  if (st == APR_EDEVICE) set_error("scan_u32: device failure");
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Tree derivation, one level L per launch, one wave per tree row.
+// Tree row (L, z, x) holds the sorted distinct y/2 over the particles of the
+// level-(L+1) rows (2z+a, 2x+b) and the tree nodes of those rows.
+// Pass 1 (FILL=false) writes the row's node count into rows_io[row];
+// pass 2 (FILL=true) reads the exclusive offset from rows_io[row], writes the
+// nodes and replaces rows_io[row] by the inclusive end.
+// ---------------------------------------------------------------------------
+constexpr int kTreeWaves = 4;
+constexpr int kMaxBitmapWords = (65536 / 2) / 32;   // parent y < 32768
+
+template <bool FILL>
+__global__ __launch_bounds__(64 * kTreeWaves) void tree_rows_kernel(
+    Meta m, int L, const uint16_t* __restrict__ py, const uint32_t* __restrict__ pend,
+    const uint16_t* __restrict__ cy, const uint32_t* __restrict__ cend, uint32_t* rows_io,
+    uint16_t* __restrict__ out_y) {
+  __shared__ uint32_t bitmap[kTreeWaves][kMaxBitmapWords];
+  const int wave = threadIdx.x / 64;
+  const uint32_t lane = lane_id();
+  const int64_t nrows = int64_t(m.dz[L]) * m.dx[L];
+  const int64_t row = int64_t(blockIdx.x) * kTreeWaves + wave;
+  if (row >= nrows) return;
+  const int z = int(row / m.dx[L]);
+  const int x = int(row % m.dx[L]);
+  const int C = L + 1;
+  const bool has_p = (C >= m.l_min && C <= m.l_max);
+  const bool has_t = (C <= m.t_hi);
+  uint32_t lb[8], le[8];
+  const uint16_t* ly[8];
+  int nl = 0;
+  uint32_t total = 0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int cz = 2 * z + a, cx = 2 * x + b;
+      if (cz >= m.dz[C] || cx >= m.dx[C]) continue;
+      if (has_p) {
+        row_range(pend, m.prow[C] + uint32_t(cz) * m.dx[C] + cx, lb[nl], le[nl]);
+        ly[nl] = py;
+        total += le[nl] - lb[nl];
+        ++nl;
+      }
+      if (has_t) {
+        row_range(cend, uint32_t(cz) * m.dx[C] + cx, lb[nl], le[nl]);
+        ly[nl] = cy;
+        total += le[nl] - lb[nl];
+        ++nl;
+      }
+    }
+  if (total == 0) {
+    // FILL: the inclusive end equals the exclusive offset already stored
+    if (!FILL && lane == 0) rows_io[row] = 0;
+    return;
+  }
+  uint32_t* bm = bitmap[wave];
+  const int nwords = (m.dy[L] + 31) / 32;
+  for (int w = lane; w < nwords; w += 64) bm[w] = 0u;
+  wave_lds_sync();
+  for (int j = 0; j < nl; ++j)
+    for (uint32_t i = lb[j] + lane; i < le[j]; i += 64) {
+      const uint32_t h = uint32_t(ly[j][i]) >> 1;
+      atomicOr(&bm[h >> 5], 1u << (h & 31));
+    }
+  wave_lds_sync();
+  if (!FILL) {
+    uint32_t c = 0;
+    for (int w = lane; w < nwords; w += 64) c += __popc(bm[w]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane == 0) rows_io[row] = c;
+    return;
+  }
+  uint32_t base = rows_io[row];
+  for (int w0 = 0; w0 < nwords; w0 += 64) {
+    const int w = w0 + int(lane);
+    uint32_t word = (w < nwords) ? bm[w] : 0u;
+    const uint32_t c = __popc(word);
+    const uint32_t incl = wave_incl_scan(c);
+    uint32_t pos = base + incl - c;
+    while (word) {
+      const int bit = __ffs(word) - 1;
+      out_y[pos++] = uint16_t(w * 32 + bit);
+      word &= word - 1u;
+    }
+    base += __shfl(incl, 63, 64);
+  }
+  if (lane == 0) rows_io[row] = base;
+}
+
+__global__ void add_offset_kernel(uint32_t* data, int64_t n, uint32_t off) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) data[i] += off;
+}
+
+// ---------------------------------------------------------------------------
+// Validation: one wave per tree row, one lane per node.
+// bit 0: partition (a node coincides with a particle, or an in-image child of
+//        a node is neither particle nor node);
+// bit 1: balance (a 26-neighbour of a node at level >= l_min lies inside a
+//        coarser particle: neither particle nor node at the node's level).
+// ---------------------------------------------------------------------------
+__device__ inline bool row_has(const uint16_t* ys, const uint32_t* ends, uint32_t row, uint32_t y) {
+  uint32_t b, e;
+  row_range(ends, row, b, e);
+  while (b < e) {
+    const uint32_t mid = (b + e) >> 1;
+    if (ys[mid] < y)
+      b = mid + 1;
+    else
+      e = mid;
+  }
+  return b < ends[row] && ys[b] == y;
+}
+
+__device__ inline bool cell_exists(const Meta& m, const uint16_t* py, const uint32_t* pend,
+                                   const uint16_t* ty, const uint32_t* tend, int l, int z, int x,
+                                   int y) {
+  if (l >= m.l_min && l <= m.l_max &&
+      row_has(py, pend, m.prow[l] + uint32_t(z) * m.dx[l] + x, uint32_t(y)))
+    return true;
+  if (l >= m.t_lo && l <= m.t_hi &&
+      row_has(ty, tend, m.trow[l] + uint32_t(z) * m.dx[l] + x, uint32_t(y)))
+    return true;
+  return false;
+}
+
+__global__ __launch_bounds__(256) void validate_kernel(Meta m, const uint16_t* __restrict__ py,
+                                                       const uint32_t* __restrict__ pend,
+                                                       const uint16_t* __restrict__ ty,
+                                                       const uint32_t* __restrict__ tend,
+                                                       int64_t n_trows, uint32_t* flags) {
+  const int64_t row = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+  if (row >= n_trows) return;
+  int L = m.t_lo;
+  while (L < m.t_hi && uint32_t(row) >= m.trow[L + 1]) ++L;
+  const uint32_t r = uint32_t(row) - m.trow[L];
+  const int z = int(r / m.dx[L]), x = int(r % m.dx[L]);
+  uint32_t b, e;
+  row_range(tend, uint32_t(row), b, e);
+  uint32_t bad = 0;
+  for (uint32_t i = b + lane_id(); i < e; i += 64) {
+    const int y = ty[i];
+    if (L >= m.l_min && row_has(py, pend, m.prow[L] + uint32_t(z) * m.dx[L] + x, uint32_t(y)))
+      bad |= 1u;
+    const int C = L + 1;
+    for (int a = 0; a < 2; ++a)
+      for (int bb = 0; bb < 2; ++bb)
+        for (int c = 0; c < 2; ++c) {
+          const int cz = 2 * z + a, cx = 2 * x + bb, cyv = 2 * y + c;
+          if (cz >= m.dz[C] || cx >= m.dx[C] || cyv >= m.dy[C]) continue;
+          if (!cell_exists(m, py, pend, ty, tend, C, cz, cx, cyv)) bad |= 1u;
+        }
+    if (L >= m.l_min) {
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dx = -1; dx <= 1; ++dx)
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int nz = z + dz, nx = x + dx, ny = y + dy;
+            if (nz < 0 || nx < 0 || ny < 0 || nz >= m.dz[L] || nx >= m.dx[L] || ny >= m.dy[L])
+              continue;
+            if (!cell_exists(m, py, pend, ty, tend, L, nz, nx, ny)) bad |= 2u;
+          }
+    }
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Non-empty tile list (Section 5.2 pre-pass): a tile of kTileZ x kTileX
+// particle rows at one level is kept if any of its rows holds a particle.
+// Tiles are enumerated finest level first.
+// ---------------------------------------------------------------------------
+struct TileLevels {
+  int32_t n_levels;
+  int32_t level[kMaxL];
+  int64_t first[kMaxL + 1];   // first tile index of each entry
+  int32_t ntx[kMaxL];
+};
+
+__device__ inline void tile_locate(const TileLevels& tl, int64_t t, int& l, int& tz, int& tx) {
+  int j = 0;
+  while (j + 1 < tl.n_levels && t >= tl.first[j + 1]) ++j;
+  l = tl.level[j];
+  const int64_t r = t - tl.first[j];
+  tz = int(r / tl.ntx[j]);
+  tx = int(r % tl.ntx[j]);
+}
+
+__global__ void tile_flag_kernel(Meta m, TileLevels tl, const uint32_t* __restrict__ pend,
+                                 uint32_t* flags, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int l, tz, tx;
+  tile_locate(tl, t, l, tz, tx);
+  uint32_t any = 0;
+  for (int a = 0; a < kTileZ; ++a)
+    for (int b = 0; b < kTileX; ++b) {
+      const int z = tz * kTileZ + a, x = tx * kTileX + b;
+      if (z >= m.dz[l] || x >= m.dx[l]) continue;
+      uint32_t rb, re;
+      row_range(pend, m.prow[l] + uint32_t(z) * m.dx[l] + x, rb, re);
+      any |= (re > rb);
+    }
+  flags[t] = any;
+}
+
+__global__ void tile_compact_kernel(TileLevels tl, const uint32_t* __restrict__ flags_scanned,
+                                    const uint32_t* __restrict__ flags_raw, uint64_t* out,
+                                    int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n || !flags_raw[t]) return;
+  int l, tz, tx;
+  tile_locate(tl, t, l, tz, tx);
+  out[flags_scanned[t]] = tile_pack(l, tz, tx);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static int finest_level(const int32_t* dims) {
+  int32_t mx = std::max(dims[0], std::max(dims[1], dims[2]));
+  int l = 0;
+  while ((int64_t(1) << l) < mx) ++l;
+  return l;
+}
+
+template <typename T>
+static apr_status dev_alloc(apr_handle* h, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) return APR_OK;
+  void* q = nullptr;
+  if (hipMalloc(&q, size_t(count) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    APR_FAIL(APR_ENOMEM, "hipMalloc failed (" + std::to_string(count * sizeof(T)) + " bytes)");
+  }
+  h->allocs.push_back(q);
+  h->device_bytes += count * int64_t(sizeof(T));
+  *p = static_cast<T*>(q);
+  return APR_OK;
+}
+
+static void free_handle(apr_handle* h) {
+  if (!h) return;
+  for (void* p : h->allocs) (void)hipFree(p);
+  delete h;
+}
+
+#define APR_TRY(expr)                 \
+  do {                                \
+    apr_status _s = (expr);           \
+    if (_s != APR_OK) {               \
+      free_handle(h);                 \
+      for (void* p : tmp) (void)hipFree(p); \
+      return _s;                      \
+    }                                 \
+  } while (0)
+
+#define APR_TRY_HIP(call)                                                       \
+  do {                                                                          \
+    hipError_t _e = (call);                                                     \
+    if (_e != hipSuccess) {                                                     \
+      set_error(std::string(#call) + ": " + hipGetErrorString(_e));             \
+      free_handle(h);                                                           \
+      for (void* p : tmp) (void)hipFree(p);                                           \
+      return APR_EDEVICE;                                                       \
+    }                                                                           \
+  } while (0)
+
+static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle** out) {
+  if (!d || !out) APR_FAIL(APR_EINVAL, "apr_access_build: null argument");
+  *out = nullptr;
+  for (int a = 0; a < 3; ++a)
+    if (d->dims[a] <= 0) APR_FAIL(APR_EINVAL, "apr_access_build: image dims must be positive");
+  if (d->dims[2] > 65535)
+    APR_FAIL(APR_EUNSUPPORTED, "apr_access_build: y size above 65535 (16-bit y indices)");
+  const int lmax = finest_level(d->dims);
+  if (d->l_max != lmax)
+    APR_FAIL(APR_EINVAL, "apr_access_build: l_max must be ceil(log2(max dim)) = " +
+                             std::to_string(lmax));
+  if (d->l_min < 0 || d->l_min > d->l_max)
+    APR_FAIL(APR_EINVAL, "apr_access_build: need 0 <= l_min <= l_max");
+  if (lmax >= kMaxL) APR_FAIL(APR_EUNSUPPORTED, "apr_access_build: too many levels");
+  if (d->n_particles < 0 || d->n_particles >= int64_t(0xffffffffu))
+    APR_FAIL(APR_EUNSUPPORTED, "apr_access_build: particle count must be below 2^32-1");
+  if (d->n_particles > 0 && !d->y_idx) APR_FAIL(APR_EINVAL, "apr_access_build: y_idx is null");
+  if (!d->xz_end) APR_FAIL(APR_EINVAL, "apr_access_build: xz_end is null");
+
+  Meta m{};
+  m.l_min = d->l_min;
+  m.l_max = lmax;
+  m.t_lo = std::max(d->l_min - 1, 0);
+  m.t_hi = lmax - 1;
+  for (int l = 0; l <= lmax; ++l) {
+    const int64_t sh = int64_t(1) << (lmax - l);
+    m.dz[l] = int32_t((d->dims[0] + sh - 1) / sh);
+    m.dx[l] = int32_t((d->dims[1] + sh - 1) / sh);
+    m.dy[l] = int32_t((d->dims[2] + sh - 1) / sh);
+  }
+  int64_t nrows = 0;
+  for (int l = d->l_min; l <= lmax; ++l) {
+    if (nrows > int64_t(0xffffffffu)) APR_FAIL(APR_EUNSUPPORTED, "too many rows");
+    m.prow[l] = uint32_t(nrows);
+    nrows += int64_t(m.dz[l]) * m.dx[l];
+  }
+  if (d->n_rows != nrows)
+    APR_FAIL(APR_EINVAL, "apr_access_build: n_rows = " + std::to_string(d->n_rows) +
+                             ", expected " + std::to_string(nrows));
+  int64_t ntrows = 0;
+  for (int l = m.t_lo; l <= m.t_hi; ++l) {
+    m.trow[l] = uint32_t(ntrows);
+    ntrows += int64_t(m.dz[l]) * m.dx[l];
+  }
+
+  // host validation of the LinearAccess arrays
+  std::vector<uint32_t> ends(static_cast<size_t>(nrows));
+  apr_handle* h = new apr_handle();
+  std::vector<void*> tmp;
+  h->meta = m;
+  h->n_p = d->n_particles;
+  h->n_rows = nrows;
+  h->n_trows = ntrows;
+  {
+    uint64_t prev = 0;
+    for (int l = d->l_min; l <= lmax; ++l) {
+      const int64_t rows_l = int64_t(m.dz[l]) * m.dx[l];
+      const uint64_t lev_begin = prev;
+      for (int64_t r = 0; r < rows_l; ++r) {
+        const int64_t row = m.prow[l] + r;
+        const uint64_t e = d->xz_end[row];
+        if (e < prev || e > uint64_t(d->n_particles)) {
+          free_handle(h);
+          APR_FAIL(APR_EINVAL, "apr_access_build: xz_end not monotone or beyond n_particles at row " +
+                                   std::to_string(row));
+        }
+        for (uint64_t i = prev; i < e; ++i) {
+          if (d->y_idx[i] >= m.dy[l] || (i > prev && d->y_idx[i] <= d->y_idx[i - 1])) {
+            free_handle(h);
+            APR_FAIL(APR_EINVAL, "apr_access_build: y_idx out of range or not strictly increasing "
+                                 "in row " + std::to_string(row));
+          }
+        }
+        ends[size_t(row)] = uint32_t(e);
+        prev = e;
+      }
+      h->per_level_p[l] = int64_t(prev - lev_begin);
+    }
+    if (prev != uint64_t(d->n_particles)) {
+      free_handle(h);
+      APR_FAIL(APR_EINVAL, "apr_access_build: last xz_end must equal n_particles");
+    }
+  }
+
+  (void)hipGetDevice(&h->device);
+  APR_TRY(dev_alloc(h, &h->py, h->n_p));
+  APR_TRY(dev_alloc(h, &h->pend, nrows));
+  if (h->n_p) APR_TRY_HIP(hipMemcpyAsync(h->py, d->y_idx, size_t(h->n_p) * 2, hipMemcpyHostToDevice, s));
+  APR_TRY_HIP(hipMemcpyAsync(h->pend, ends.data(), size_t(nrows) * 4, hipMemcpyHostToDevice, s));
+  APR_TRY_HIP(hipStreamSynchronize(s));
+
+  // ---- tree, finest level first; per-level local arrays
+  std::vector<uint16_t*> lev_y(kMaxL, nullptr);
+  std::vector<uint32_t*> lev_end(kMaxL, nullptr);
+  std::vector<uint32_t> lev_n(kMaxL, 0);
+  uint32_t* d_total = nullptr;
+  {
+    void* q = nullptr;
+    APR_TRY_HIP(hipMalloc(&q, sizeof(uint32_t)));
+    tmp.push_back(q);
+    d_total = static_cast<uint32_t*>(q);
+  }
+  for (int L = m.t_hi; L >= m.t_lo; --L) {
+    const int64_t rows_l = int64_t(m.dz[L]) * m.dx[L];
+    void* q = nullptr;
+    APR_TRY_HIP(hipMalloc(&q, size_t(rows_l) * 4));
+    tmp.push_back(q);
+    lev_end[L] = static_cast<uint32_t*>(q);
+    const unsigned grid = unsigned((rows_l + kTreeWaves - 1) / kTreeWaves);
+    const uint16_t* cy = (L + 1 <= m.t_hi) ? lev_y[L + 1] : nullptr;
+    const uint32_t* cend = (L + 1 <= m.t_hi) ? lev_end[L + 1] : nullptr;
+    hipLaunchKernelGGL(tree_rows_kernel<false>, dim3(grid), dim3(64 * kTreeWaves), 0, s, m, L,
+                       h->py, h->pend, cy, cend, lev_end[L], nullptr);
+    APR_TRY_HIP(hipGetLastError());
+    APR_TRY(scan_u32(lev_end[L], rows_l, d_total, s));
+    uint32_t tot = 0;
+    APR_TRY_HIP(hipMemcpyAsync(&tot, d_total, 4, hipMemcpyDeviceToHost, s));
+    APR_TRY_HIP(hipStreamSynchronize(s));
+    lev_n[L] = tot;
+    if (tot) {
+      APR_TRY_HIP(hipMalloc(&q, size_t(tot) * 2));
+      tmp.push_back(q);
+      lev_y[L] = static_cast<uint16_t*>(q);
+    }
+    hipLaunchKernelGGL(tree_rows_kernel<true>, dim3(grid), dim3(64 * kTreeWaves), 0, s, m, L,
+                       h->py, h->pend, cy, cend, lev_end[L], lev_y[L]);
+    APR_TRY_HIP(hipGetLastError());
+  }
+  int64_t nt = 0;
+  for (int L = m.t_lo; L <= m.t_hi; ++L) {
+    nt += lev_n[L];
+    h->per_level_t[L] = lev_n[L];
+  }
+  if (nt >= int64_t(0xffffffffu)) APR_TRY(APR_EUNSUPPORTED);
+  h->n_t = nt;
+  APR_TRY(dev_alloc(h, &h->ty, nt));
+  APR_TRY(dev_alloc(h, &h->tend, ntrows));
+  {
+    uint32_t base = 0;
+    for (int L = m.t_lo; L <= m.t_hi; ++L) {
+      const int64_t rows_l = int64_t(m.dz[L]) * m.dx[L];
+      if (lev_n[L])
+        APR_TRY_HIP(hipMemcpyAsync(h->ty + base, lev_y[L], size_t(lev_n[L]) * 2,
+                                   hipMemcpyDeviceToDevice, s));
+      APR_TRY_HIP(hipMemcpyAsync(h->tend + m.trow[L], lev_end[L], size_t(rows_l) * 4,
+                                 hipMemcpyDeviceToDevice, s));
+      if (base)
+        hipLaunchKernelGGL(add_offset_kernel, dim3(unsigned((rows_l + 255) / 256)), dim3(256), 0,
+                           s, h->tend + m.trow[L], rows_l, base);
+      APR_TRY_HIP(hipGetLastError());
+      base += lev_n[L];
+    }
+  }
+
+  // ---- validation
+  if (d->flags & (APR_VALIDATE_PARTITION | APR_VALIDATE_BALANCE)) {
+    // level l_min must be fully covered by its particles and tree nodes
+    const int64_t full = int64_t(m.dz[m.l_min]) * m.dx[m.l_min] * m.dy[m.l_min];
+    const int64_t have = h->per_level_p[m.l_min] + (m.l_min <= m.t_hi ? h->per_level_t[m.l_min] : 0);
+    uint32_t bad = (have != full) ? 1u : 0u;
+    if (ntrows > 0) {
+      APR_TRY_HIP(hipMemsetAsync(d_total, 0, 4, s));
+      hipLaunchKernelGGL(validate_kernel, dim3(unsigned((ntrows + 3) / 4)), dim3(256), 0, s, m,
+                         h->py, h->pend, h->ty, h->tend, ntrows, d_total);
+      APR_TRY_HIP(hipGetLastError());
+      uint32_t f = 0;
+      APR_TRY_HIP(hipMemcpyAsync(&f, d_total, 4, hipMemcpyDeviceToHost, s));
+      APR_TRY_HIP(hipStreamSynchronize(s));
+      bad |= f;
+    }
+    if ((d->flags & APR_VALIDATE_PARTITION) && (bad & 1u)) {
+      set_error("apr_access_build: particle cells do not partition the image");
+      free_handle(h);
+      for (void* p : tmp) (void)hipFree(p);
+      return APR_EPARTITION;
+    }
+    if ((d->flags & APR_VALIDATE_BALANCE) && (bad & 2u)) {
+      set_error("apr_access_build: neighbouring particle levels differ by more than one");
+      free_handle(h);
+      for (void* p : tmp) (void)hipFree(p);
+      return APR_EUNBALANCED;
+    }
+  }
+
+  // ---- tile list
+  {
+    TileLevels tl{};
+    int64_t ntot = 0;
+    for (int l = lmax; l >= d->l_min; --l) {
+      const int j = tl.n_levels++;
+      tl.level[j] = l;
+      tl.first[j] = ntot;
+      tl.ntx[j] = (m.dx[l] + kTileX - 1) / kTileX;
+      ntot += int64_t((m.dz[l] + kTileZ - 1) / kTileZ) * tl.ntx[j];
+    }
+    tl.first[tl.n_levels] = ntot;
+    void* q = nullptr;
+    APR_TRY_HIP(hipMalloc(&q, size_t(ntot + 1) * 4));
+    tmp.push_back(q);
+    uint32_t* raw = static_cast<uint32_t*>(q);
+    void* q2 = nullptr;
+    APR_TRY_HIP(hipMalloc(&q2, size_t(ntot + 1) * 4));
+    tmp.push_back(q2);
+    uint32_t* sc = static_cast<uint32_t*>(q2);
+    hipLaunchKernelGGL(tile_flag_kernel, dim3(unsigned((ntot + 255) / 256)), dim3(256), 0, s, m,
+                       tl, h->pend, raw, ntot);
+    APR_TRY_HIP(hipGetLastError());
+    APR_TRY_HIP(hipMemcpyAsync(sc, raw, size_t(ntot) * 4, hipMemcpyDeviceToDevice, s));
+    APR_TRY(scan_u32(sc, ntot, d_total, s));
+    uint32_t nkeep = 0;
+    APR_TRY_HIP(hipMemcpyAsync(&nkeep, d_total, 4, hipMemcpyDeviceToHost, s));
+    APR_TRY_HIP(hipStreamSynchronize(s));
+    h->n_tiles = nkeep;
+    APR_TRY(dev_alloc(h, &h->tiles, std::max<int64_t>(nkeep, 1)));
+    hipLaunchKernelGGL(tile_compact_kernel, dim3(unsigned((ntot + 255) / 256)), dim3(256), 0, s,
+                       tl, sc, raw, h->tiles, ntot);
+    APR_TRY_HIP(hipGetLastError());
+  }
+  APR_TRY_HIP(hipStreamSynchronize(s));
+  for (void* p : tmp) (void)hipFree(p);
+  *out = h;
+  return APR_OK;
+}
+
+}  // namespace apr
+
+using namespace apr;
+
+extern "C" {
+
+const char* apr_last_error(void) { return g_last_error.c_str(); }
+
+apr_status apr_access_build(const apr_access_desc* desc, void* stream, apr_handle** out) {
+  g_last_error.clear();
+  try {
+    return build_impl(desc, static_cast<hipStream_t>(stream), out);
+  } catch (const std::exception& e) {
+    set_error(std::string("apr_access_build: ") + e.what());
+    return APR_ENOMEM;
+  } catch (...) {
+    set_error("apr_access_build: unknown failure");
+    return APR_EDEVICE;
+  }
+}
+
+apr_status apr_access_get_info(const apr_handle* h, apr_access_info* o) {
+  if (!h || !o) APR_FAIL(APR_EINVAL, "apr_access_get_info: null argument");
+  std::memset(o, 0, sizeof(*o));
+  o->n_particles = h->n_p;
+  o->n_tree = h->n_t;
+  o->n_rows = h->n_rows;
+  o->n_tree_rows = h->n_trows;
+  o->l_min = h->meta.l_min;
+  o->l_max = h->meta.l_max;
+  o->tree_l_min = h->meta.t_lo;
+  o->tree_l_max = h->meta.t_hi;
+  for (int l = 0; l <= h->meta.l_max; ++l) {
+    o->dims[l][0] = h->meta.dz[l];
+    o->dims[l][1] = h->meta.dx[l];
+    o->dims[l][2] = h->meta.dy[l];
+    o->particles_per_level[l] = h->per_level_p[l];
+    o->tree_per_level[l] = h->per_level_t[l];
+  }
+  o->n_tiles = h->n_tiles;
+  o->device_bytes = h->device_bytes;
+  return APR_OK;
+}
+
+apr_status apr_access_export_tree(const apr_handle* h, uint16_t* ty, uint64_t* tend) {
+  if (!h) APR_FAIL(APR_EINVAL, "apr_access_export_tree: null handle");
+  if (ty && h->n_t) APR_HIP(hipMemcpy(ty, h->ty, size_t(h->n_t) * 2, hipMemcpyDeviceToHost));
+  if (tend && h->n_trows) {
+    std::vector<uint32_t> e(static_cast<size_t>(h->n_trows));
+    APR_HIP(hipMemcpy(e.data(), h->tend, size_t(h->n_trows) * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < h->n_trows; ++i) tend[i] = e[size_t(i)];
+  }
+  return APR_OK;
+}
+
+apr_status apr_access_destroy(apr_handle* h) {
+  free_handle(h);
+  return APR_OK;
+}
+
+}  // extern "C"

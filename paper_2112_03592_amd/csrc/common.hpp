@@ -1,0 +1,116 @@
+// Shared definitions of the aprconv HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "aprconv.h"
+
+namespace apr {
+
+constexpr int kMaxL = APR_MAX_LEVELS;
+constexpr uint32_t kNoY = 0x7fffffffu;   // "no further element" marker for y searches
+
+// Per-level geometry, passed by value to kernels.
+struct Meta {
+  int32_t l_min, l_max, t_lo, t_hi;      // particle levels, tree levels (t_hi < t_lo: no tree)
+  int32_t dz[kMaxL], dx[kMaxL], dy[kMaxL];
+  uint32_t prow[kMaxL];                  // first particle row of level l
+  uint32_t trow[kMaxL];                  // first tree row of level l
+};
+
+// Tile descriptor of the convolution work list: level, tile z, tile x.
+__host__ __device__ inline uint64_t tile_pack(int l, int tz, int tx) {
+  return (uint64_t(l) << 48) | (uint64_t(uint32_t(tz)) << 24) | uint64_t(uint32_t(tx));
+}
+__host__ __device__ inline void tile_unpack(uint64_t t, int& l, int& tz, int& tx) {
+  l = int(t >> 48);
+  tz = int((t >> 24) & 0xffffffu);
+  tx = int(t & 0xffffffu);
+}
+
+constexpr int kTileZ = 4;   // output rows per tile along z
+constexpr int kTileX = 4;   // output rows per tile along x
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// number of set bits of m below this lane
+__device__ inline uint32_t mask_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+}
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+
+// LDS writes by some lanes of a wave become visible to the other lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void row_range(const uint32_t* __restrict__ ends, uint32_t row, uint32_t& b,
+                                 uint32_t& e) {
+  e = ends[row];
+  b = row ? ends[row - 1] : 0u;
+}
+
+// Storage conversions (FP32 arithmetic everywhere).
+template <typename T> __device__ inline float to_f32(T v);
+template <> __device__ inline float to_f32<float>(float v) { return v; }
+template <> __device__ inline float to_f32<__hip_bfloat16>(__hip_bfloat16 v) {
+  return __bfloat162float(v);
+}
+template <typename T> __device__ inline T from_f32(float v);
+template <> __device__ inline float from_f32<float>(float v) { return v; }
+template <> __device__ inline __hip_bfloat16 from_f32<__hip_bfloat16>(float v) {
+  return __float2bfloat16(v);   // round to nearest even
+}
+
+// ---------------------------------------------------------------------------
+// Host-side state and error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define APR_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t _e = (call);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      ::apr::set_error(std::string(#call) + ": " + hipGetErrorString(_e));         \
+      return APR_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define APR_FAIL(code, msg)    \
+  do {                         \
+    ::apr::set_error(msg);     \
+    return (code);             \
+  } while (0)
+
+// Exclusive scan of n uint32 values in place on `stream`; returns the total in
+// *total_dev (device uint32, may be nullptr).
+apr_status scan_u32(uint32_t* data, int64_t n, uint32_t* total_dev, hipStream_t stream);
+
+}  // namespace apr
+
+struct apr_handle {
+  int device = 0;
+  apr::Meta meta{};
+  int64_t n_p = 0, n_t = 0, n_rows = 0, n_trows = 0;
+  int64_t per_level_p[apr::kMaxL] = {0};
+  int64_t per_level_t[apr::kMaxL] = {0};
+  uint16_t* py = nullptr;     // particle y [n_p]
+  uint32_t* pend = nullptr;   // particle row ends [n_rows]
+  uint16_t* ty = nullptr;     // tree y [n_t]
+  uint32_t* tend = nullptr;   // tree row ends [n_trows]
+  uint64_t* tiles = nullptr;  // conv tiles [n_tiles], finest level first
+  int64_t n_tiles = 0;
+  int64_t device_bytes = 0;
+  std::vector<void*> allocs;
+};

@@ -1,0 +1,102 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+entry point, computes per-level stencils on the host like the oracle, and
+rejects malformed access structures before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from aprgen.apr_input import random_apr
+from oracle.stencil import ADAPTIVE, RESTRICT, SAME, flip, level_stencils
+from paper_2112_03592_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "aprconv.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="libaprconv.so not built")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:apr_status|const char\*)\s+(apr_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["apr_access_build", "apr_fill_tree", "apr_conv", "apr_last_error"]:
+        assert n in names
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("mode,omode", [(0, SAME), (1, RESTRICT), (2, ADAPTIVE)])
+@pytest.mark.parametrize("k", [3, 5])
+@pytest.mark.parametrize("do_flip", [0, 1])
+def test_stencil_levels_match_oracle(mode, omode, k, do_flip):
+    from paper_2112_03592_amd.apr import stencil_levels
+    rng = np.random.default_rng(k + 7 * mode)
+    w = rng.normal(size=(2, 3, k, k, k))
+    got = stencil_levels(w, omode, k, 2, 9, flip=bool(do_flip))
+    ref = level_stencils(flip(w) if do_flip else w, omode, 2, 9)
+    assert got.shape == ref.shape
+    assert np.allclose(got, ref.astype(np.float32), rtol=1e-6, atol=1e-7)
+
+
+def _build_raw(dims, l_min, l_max, y, e, flags=0):
+    lib = L.load()
+    d = L.AccessDesc()
+    d.dims[:] = list(dims)
+    d.l_min, d.l_max = l_min, l_max
+    y = np.ascontiguousarray(y, np.uint16)
+    e = np.ascontiguousarray(e, np.uint64)
+    d.y_idx = y.ctypes.data if y.size else None
+    d.n_particles = y.size
+    d.xz_end = e.ctypes.data if e.size else None
+    d.n_rows = e.size
+    d.flags = flags
+    h = ctypes.c_void_p()
+    st = lib.apr_access_build(ctypes.byref(d), None, ctypes.byref(h))
+    return st, lib.apr_last_error().decode()
+
+
+def test_build_rejects_malformed_arrays_on_the_host():
+    inp = random_apr((8, 8, 8), l_min=1, seed=1)
+    e = inp.xz_end.copy()
+    # non-monotone row ends
+    bad = e.copy()
+    bad[-1] = bad[-2] - 1 if bad[-2] > 0 else 0
+    bad[-2] = e[-1]
+    st, msg = _build_raw(inp.dims, inp.l_min, inp.l_max, inp.y_idx, bad)
+    assert st == L.APR_EINVAL
+    # wrong l_max
+    st, msg = _build_raw(inp.dims, inp.l_min, inp.l_max + 1, inp.y_idx, e)
+    assert st == L.APR_EINVAL and "l_max" in msg
+    # wrong row count
+    st, _ = _build_raw(inp.dims, inp.l_min, inp.l_max, inp.y_idx, e[:-1])
+    assert st == L.APR_EINVAL
+    # y out of range in its row
+    y = inp.y_idx.copy()
+    y[-1] = 60000
+    st, msg = _build_raw(inp.dims, inp.l_min, inp.l_max, y, e)
+    assert st == L.APR_EINVAL and "y_idx" in msg
+    # y not increasing within a row
+    y = inp.y_idx.copy()
+    rows = np.searchsorted(e, np.arange(y.size), side="right")
+    same = np.nonzero(rows[1:] == rows[:-1])[0]
+    j = int(same[0])
+    y[j], y[j + 1] = y[j + 1], y[j]
+    st, msg = _build_raw(inp.dims, inp.l_min, inp.l_max, y, e)
+    assert st == L.APR_EINVAL
+    # 16-bit y limit
+    st, msg = _build_raw((4, 4, 70000), 0, 17, np.zeros(0), np.zeros(0))
+    assert st in (L.APR_EUNSUPPORTED, L.APR_EINVAL)
+    # last row end must equal the particle count
+    st, _ = _build_raw(inp.dims, inp.l_min, inp.l_max, inp.y_idx[:-1], e)
+    assert st == L.APR_EINVAL

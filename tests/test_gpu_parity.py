@@ -1,0 +1,253 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Bars (from the design targets): access/tree/neighbour indexing bit-exact;
+FP32 outputs within 1e-5 * M_p where M_p = sum_o |w_l[o]| |V_l(c_p+o)|;
+BF16 storage within 1e-2 * M_p."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from aprgen.apr_input import cached_sphere_apr, random_apr
+from oracle import access as A
+from oracle import conv as C
+from oracle import stencil as S
+from oracle.tree import fill_tree as oracle_fill
+from tests.gpu_common import (SMALL_CASES, assert_close_scaled, encode_oracle_map, linear_access)
+
+pytestmark = pytest.mark.gpu
+
+from paper_2112_03592_amd import apr as G  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    G.AprAccess  # library must be loadable
+    from paper_2112_03592_amd import _lib
+    _lib.load()
+
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        inp = SMALL_CASES[name]()
+        la = linear_access(inp)
+        tr = A.tree_structure(la)
+        _cache[name] = (inp, la, tr)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_tree_structure_bit_exact(name):
+    say("tree structure", name)
+    inp, la, tr = case(name)
+    with G.AprAccess.from_input(inp) as acc:
+        ty, te = acc.export_tree()
+        assert acc.n_tree == tr.n
+        assert np.array_equal(ty.astype(np.int64), tr.y_idx)
+        assert np.array_equal(te.astype(np.int64), tr.xz_end)
+        assert (acc.tree_l_min, acc.tree_l_max) == (tr.l_min, tr.l_max)
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_fill_tree_fp32(name):
+    say("fill tree", name)
+    inp, la, tr = case(name)
+    ref = oracle_fill(la, tr, inp.values.astype(np.float64))
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(inp.values).cuda()
+        t = G.fill_tree(acc, x).cpu().numpy().astype(np.float64)
+    # mean of <= 8 positive children per level, FP32
+    assert np.allclose(t, ref, rtol=4e-6, atol=0)
+
+
+def _weights(k, mode, la, seed):
+    rng = np.random.default_rng(seed)
+    if mode == "explicit":
+        w = rng.normal(size=(la.l_max - la.l_min + 1, k, k, k)).astype(np.float32)
+        return w
+    if mode == "asym":
+        w = rng.normal(size=(k, k, k))
+        return G.stencil_levels(w, "same", k, la.l_min, la.l_max)
+    return G.stencil_levels(S.gaussian_stencil(k, 1.0), mode, k, la.l_min, la.l_max)
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+@pytest.mark.parametrize("k", [3, 5])
+@pytest.mark.parametrize("mode", ["restrict", "explicit"])
+def test_conv_fp32(name, k, mode):
+    say("conv fp32", name, k, mode)
+    inp, la, tr = case(name)
+    w32 = _weights(k, mode, la, seed=k)
+    x64 = inp.values.astype(np.float64)
+    ref = C.apr_conv(la, x64, w32.astype(np.float64), tree=tr)
+    scale = C.apr_conv(la, np.abs(x64), np.abs(w32.astype(np.float64)), tree=tr)
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(inp.values).cuda()
+        t = G.fill_tree(acc, x)
+        y = G.conv(acc, x, t, torch.from_numpy(np.ascontiguousarray(w32)).cuda(), k).cpu().numpy()
+    assert_close_scaled(y, ref, scale, 1e-5, f"{name} k={k} {mode}")
+
+
+@pytest.mark.parametrize("name", ["rand16_l1", "rand33x20x70", "sphere64"])
+def test_conv_shared_stencil_and_signed_values(name):
+    inp, la, tr = case(name)
+    rng = np.random.default_rng(5)
+    xs = rng.normal(size=la.n).astype(np.float32)
+    w = rng.normal(size=(1, 5, 5, 5)).astype(np.float32)
+    ref = C.apr_conv(la, xs.astype(np.float64), w.astype(np.float64), tree=tr)
+    scale = C.apr_conv(la, np.abs(xs.astype(np.float64)), np.abs(w.astype(np.float64)), tree=tr)
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(xs).cuda()
+        t = G.fill_tree(acc, x)
+        y = G.conv(acc, x, t, torch.from_numpy(w).cuda(), 5).cpu().numpy()
+    assert_close_scaled(y, ref, scale, 1e-5, name)
+
+
+@pytest.mark.parametrize("name", ["rand8_l0", "rand9x12x7", "rand33x20x70", "rand_long_y", "sphere64",
+                                  "dense13x11x70", "single_cell"])
+@pytest.mark.parametrize("k", [3, 5])
+def test_neighbor_map_bit_exact(name, k):
+    say("neighbour map", name, k)
+    inp, la, tr = case(name)
+    sel = np.arange(la.n) if la.n <= 6000 else np.sort(np.random.default_rng(0).choice(la.n, 6000, replace=False))
+    src, idx = C.neighbor_map(la, k, sel, tree=tr)
+    ref = encode_oracle_map(src, idx)
+    with G.AprAccess.from_input(inp) as acc:
+        got = G.neighbor_map(acc, k, torch.from_numpy(sel).cuda()).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_conv_is_deterministic():
+    inp, la, tr = case("sphere64")
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(inp.values).cuda()
+        w = torch.from_numpy(_weights(5, "restrict", la, 0)).cuda()
+        t1 = G.fill_tree(acc, x)
+        y1 = G.conv(acc, x, t1, w, 5)
+        t2 = G.fill_tree(acc, x)
+        y2 = G.conv(acc, x, t2, w, 5)
+        assert torch.equal(t1, t2) and torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("name", ["rand16_l1", "sphere64"])
+@pytest.mark.parametrize("k", [3, 5])
+def test_conv_bf16_storage(name, k):
+    """BF16 particle and tree storage, FP32 accumulation: within 1e-2 * M_p of
+    the oracle on the BF16-rounded particle values."""
+    inp, la, tr = case(name)
+    w32 = _weights(k, "restrict", la, 0)
+    with G.AprAccess.from_input(inp) as acc:
+        xb = torch.from_numpy(inp.values).cuda().to(torch.bfloat16)
+        x64 = xb.float().cpu().numpy().astype(np.float64)
+        ref = C.apr_conv(la, x64, w32.astype(np.float64), tree=tr)
+        scale = C.apr_conv(la, np.abs(x64), np.abs(w32.astype(np.float64)), tree=tr)
+        t = G.fill_tree(acc, xb)
+        wd = torch.from_numpy(w32).cuda()
+        y32 = G.conv(acc, xb, t, wd, k, out_dtype=torch.float32).cpu().numpy()
+        yb = G.conv(acc, xb, t, wd, k).float().cpu().numpy()
+    assert_close_scaled(y32, ref, scale, 1e-2, "bf16 in / fp32 out")
+    assert_close_scaled(yb, ref, scale, 1e-2, "bf16 in / bf16 out")
+
+
+def test_rl_epilogues():
+    inp, la, tr = case("sphere64")
+    psf = S.gaussian_stencil(5, 1.5)
+    wl = G.stencil_levels(psf, "restrict", 5, la.l_min, la.l_max)
+    ref_c = C.apr_conv(la, inp.values.astype(np.float64), wl.astype(np.float64), tree=tr)
+    u = np.random.default_rng(1).uniform(50, 150, la.n).astype(np.float32)
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(inp.values).cuda()
+        ud = torch.from_numpy(u).cuda()
+        t = G.fill_tree(acc, x)
+        w = torch.from_numpy(wl).cuda()
+        r = G.conv(acc, x, t, w, 5, epilogue="ratio", epi_arg=ud, eps=1e-3).cpu().numpy()
+        mres = G.conv(acc, x, t, w, 5, epilogue="mul", epi_arg=ud).cpu().numpy()
+    assert np.allclose(r, u / np.maximum(ref_c, 1e-3), rtol=2e-5)
+    assert np.allclose(mres, ref_c * u, rtol=2e-5)
+
+
+def test_validation_rejects_unbalanced_and_broken_partitions():
+    from paper_2112_03592_amd._lib import AprError, APR_EUNBALANCED, APR_EPARTITION
+    unb = None
+    for seed in range(40):
+        u = random_apr((16, 16, 16), l_min=0, seed=seed, p_refine=0.06, balanced=False)
+        if not A.check_balance(linear_access(u)):
+            unb = u
+            break
+    assert unb is not None
+    with pytest.raises(AprError) as ei:
+        G.AprAccess.from_input(unb)
+    assert ei.value.status == APR_EUNBALANCED
+    ok = random_apr((8, 8, 8), l_min=1, seed=3, p_refine=0.3)
+    # a gap: drop the last particle of the finest level
+    cells = {l: c.copy() for l, c in ok.cells.items()}
+    top = max(l for l in cells if cells[l].shape[0])
+    cells[top] = cells[top][:-1]
+    from aprgen.apr_input import encode_cells
+    y, e = encode_cells(ok.dims, ok.l_min, ok.l_max, cells)
+    with pytest.raises(AprError) as ei:
+        G.AprAccess(ok.dims, ok.l_min, ok.l_max, y, e)
+    assert ei.value.status == APR_EPARTITION
+    # an overlap: add the parent cell of a finest-level particle as a particle
+    cells = {l: c.copy() for l, c in ok.cells.items()}
+    par = cells[top][0] // 2
+    cells[top - 1] = np.unique(np.concatenate([cells[top - 1], par[None]]), axis=0)
+    y, e = encode_cells(ok.dims, ok.l_min, ok.l_max, cells)
+    with pytest.raises(AprError) as ei:
+        G.AprAccess(ok.dims, ok.l_min, ok.l_max, y, e)
+    assert ei.value.status == APR_EPARTITION
+
+
+# ---------------------------------------------------------------------------
+# Full-size sphere field (512^3, ~6.6M particles) in the launch configuration
+# the benchmark times; outputs checked on a seeded sample by keyed lookup.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def sphere512():
+    say("generating sphere512")
+    inp = cached_sphere_apr("sphere512")
+    la = linear_access(inp)
+    say("oracle tree for sphere512")
+    tr = A.tree_structure(la)
+    tv = oracle_fill(la, tr, inp.values.astype(np.float64))
+    return inp, la, tr, tv
+
+
+def test_sphere512_tree_bit_exact_and_values(sphere512):
+    inp, la, tr, tv = sphere512
+    with G.AprAccess.from_input(inp) as acc:
+        ty, te = acc.export_tree()
+        assert np.array_equal(ty.astype(np.int64), tr.y_idx)
+        assert np.array_equal(te.astype(np.int64), tr.xz_end)
+        t = G.fill_tree(acc, torch.from_numpy(inp.values).cuda()).cpu().numpy()
+    assert np.allclose(t.astype(np.float64), tv, rtol=4e-6, atol=0)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_sphere512_conv_sampled(sphere512, k):
+    inp, la, tr, tv = sphere512
+    say("sphere512 conv", k)
+    w32 = G.stencil_levels(S.gaussian_stencil(k, 1.0), "same", k, la.l_min, la.l_max)
+    smp = np.sort(np.random.default_rng(k).choice(la.n, 4096, replace=False))
+    x64 = inp.values.astype(np.float64)
+    ref = C.apr_conv_keyed(la, x64, w32.astype(np.float64), smp, tree=tr, tvals=tv)[:, 0]
+    tva = oracle_fill(la, tr, np.abs(x64))
+    scale = C.apr_conv_keyed(la, np.abs(x64), np.abs(w32.astype(np.float64)), smp, tree=tr, tvals=tva)[:, 0]
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(inp.values).cuda()
+        t = G.fill_tree(acc, x)
+        y = G.conv(acc, x, t, torch.from_numpy(w32).cuda(), k).cpu().numpy()
+        nm = G.neighbor_map(acc, k, torch.from_numpy(smp[:512]).cuda()).cpu().numpy()
+    assert_close_scaled(y[smp], ref, scale, 1e-5, f"sphere512 k={k}")
+    src, idx = C.neighbor_map(la, k, smp[:512], tree=tr)
+    assert np.array_equal(nm, encode_oracle_map(src, idx))

@@ -7,7 +7,7 @@ import pytest
 from aprgen.apr_input import random_apr
 from oracle import access as A
 from oracle.stencil import (ADAPTIVE, RESTRICT, SAME, flip, gaussian_stencil,
-                            level_stencils, restrict_stencil)
+                            level_stencils, restrict_stencil, restrict_stencil_enumerated)
 from oracle.tree import fill_tree
 
 
@@ -60,6 +60,7 @@ def test_restriction_equals_explicit_RKP(k, s, m):
     ref = _explicit_restriction(w, s, m)
     got = restrict_stencil(w, s)
     assert np.allclose(got, ref, atol=1e-13, rtol=0)
+    assert np.allclose(restrict_stencil_enumerated(w, s), ref, atol=1e-13, rtol=0)
 
 
 def test_restriction_invariants():
