@@ -30,7 +30,7 @@ SRC_PAD, SRC_SAME, SRC_COARSER, SRC_TREE, SRC_FAR = 0, 1, 2, 3, 4
 
 def _as2d(x):
     x = np.asarray(x, np.float64)
-    return x.reshape(x.shape[0], -1)
+    return x[:, None] if x.ndim == 1 else x
 
 
 def norm_weights(w, n_levels: int) -> np.ndarray:

@@ -212,8 +212,11 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
               for (int dx = 0; dx < 2; ++dx) {
                 const int hz = hz0 + dz, hx = hx0 + dx;
                 if (hz < 0 || hx < 0 || hz >= HZ || hx >= HX) continue;
+                // a coarse cell on the far edge of an odd-sized grid covers
+                // level-l cells outside the image: those stay zero padding
+                if (z0 - R + hz >= Dz || x0 - R + hx >= Dx) continue;
                 if (lo >= wlo) patch[hz * HX + hx][lo - wlo] = val;
-                if (hi <= whi) patch[hz * HX + hx][hi - wlo] = val;
+                if (hi <= whi && hi < Dy) patch[hz * HX + hx][hi - wlo] = val;
               }
           }
         }
