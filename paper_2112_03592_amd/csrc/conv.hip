@@ -26,6 +26,8 @@ namespace apr {
 
 constexpr int kYC = 64;          // output cells per chunk along y
 constexpr int kBig = 1 << 28;    // y of a lane past the end of its row
+constexpr int kBatch = 4;        // independent elements per thread in flight
+constexpr int kRowIdCap = 4096;  // patch items per chunk with a stored source row
 
 struct ConvArgs {
   Meta m;
@@ -48,6 +50,64 @@ struct ConvArgs {
   int64_t* map;         // neighbour-map mode output [n_sel][k^3]
 };
 
+// exclusive scan of n <= 192 LDS entries in place by one wave; data[n] = total
+__device__ inline void wave_scan_lds(uint32_t* data, int n) {
+  const uint32_t lane = lane_id();
+  const int b = int(lane) * 3;
+  uint32_t v0 = (b < n) ? data[b] : 0u, v1 = (b + 1 < n) ? data[b + 1] : 0u,
+           v2 = (b + 2 < n) ? data[b + 2] : 0u;
+  const uint32_t s = v0 + v1 + v2;
+  uint32_t incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= uint32_t(o)) incl += t;
+  }
+  const uint32_t ex = incl - s;
+  if (b < n) data[b] = ex;
+  if (b + 1 < n) data[b + 1] = ex + v0;
+  if (b + 2 < n) data[b + 2] = ex + v0 + v1;
+  if (lane == 63) data[n] = incl;
+}
+
+// largest r in [0, n) with pre[r] <= v (pre non-decreasing, pre[0] = 0 <= v)
+__device__ inline int find_row(const uint32_t* pre, int n, uint32_t v) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// wave 0: opre[c] = exclusive prefix of min(oe[c] - op[c], OCAP), opre[NC] = total
+template <int NC, int OCAP>
+__device__ inline void centre_caps(const uint32_t* op, const uint32_t* oe, uint32_t* opre) {
+  const uint32_t lane = lane_id();
+  const uint32_t cap = (lane < uint32_t(NC)) ? min(oe[lane] - op[lane], uint32_t(OCAP)) : 0u;
+  uint32_t incl = cap;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t tt = __shfl_up(incl, o, 64);
+    if (lane >= uint32_t(o)) incl += tt;
+  }
+  if (lane < uint32_t(NC)) opre[lane] = incl - cap;
+  if (lane == uint32_t(NC - 1)) opre[NC] = incl;
+}
+
+// wave 0: centre caps as above, then crow[item] = centre row of each item
+template <int NC, int OCAP>
+__device__ inline void centre_caps_rows(const uint32_t* op, const uint32_t* oe, uint32_t* opre,
+                                        uint8_t* crow) {
+  centre_caps<NC, OCAP>(op, oe, opre);
+  wave_lds_sync();
+  const uint32_t lane = lane_id();
+  for (int c = 0; c < NC; ++c) {
+    const uint32_t b = opre[c], n = opre[c + 1] - b;
+    for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
+  }
+}
+
 template <int K, typename TX, typename TY, bool INDEX>
 __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
   constexpr int R = K / 2;
@@ -59,16 +119,22 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
   constexpr int NC = kTileZ * kTileX;                // centre (output) rows
   constexpr int PY = kYC + 2 * R;
   constexpr int K3 = K * K * K;
+  constexpr int OCAP = kYC + 1;                      // centre-row elements examined per chunk
+  constexpr uint32_t kNone = 0xffffffffu;
   using PT = typename std::conditional<INDEX, long long, float>::type;
   static_assert(PY <= 128, "patch position packs into 7 bits");
+  static_assert(NSRC <= 192 && NC <= 64, "scan sizes");
 
   __shared__ PT patch[NH][PY];
-  __shared__ uint32_t sp[NSRC], se[NSRC];
-  __shared__ uint32_t op[NC], oe[NC];
-  __shared__ uint32_t o_idx[NC * kYC];
-  __shared__ uint16_t o_pos[NC * kYC];
-  __shared__ float wsh[K3];
-  __shared__ int s_y0[2], s_n[2], s_ymax[2];
+  __shared__ uint32_t sp[NSRC], se[NSRC], spre[NSRC + 1], scons[NSRC];
+  __shared__ int yfirst[NSRC];
+  __shared__ uint32_t op[NC], oe[NC], opre[NC + 1], ocnt[NC];
+  __shared__ int rymax[NC], rnext[NC];     // per centre row: last listed y, next y
+  __shared__ uint32_t o_idx[NC * OCAP];
+  __shared__ uint16_t o_pos[NC * OCAP];
+  __shared__ uint8_t crow[NC * OCAP];      // centre row of each listing item
+  __shared__ uint8_t srow[kRowIdCap];      // source row of each patch item
+  __shared__ int s_y0;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -81,6 +147,10 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
   if (t >= a.n_tiles) return;
   int l, tz, tx;
   tile_unpack(a.tiles[t], l, tz, tx);
+  // workgroup-uniform: keep them in scalar registers
+  l = __builtin_amdgcn_readfirstlane(l);
+  tz = __builtin_amdgcn_readfirstlane(tz);
+  tx = __builtin_amdgcn_readfirstlane(tx);
   const Meta& m = a.m;
   const int z0 = tz * kTileZ, x0 = tx * kTileX;
   const int Dz = m.dz[l], Dx = m.dx[l], Dy = m.dy[l];
@@ -88,11 +158,13 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
   const bool has_t = l <= m.t_hi;
   const TX* __restrict__ xv = static_cast<const TX*>(a.x);
   const TX* __restrict__ tv = static_cast<const TX*>(a.tree);
+  const uint16_t* __restrict__ py = a.py;
+  const uint16_t* __restrict__ ty = a.ty;
 
-  if constexpr (!INDEX) {
-    const float* wl = a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * K3;
-    for (int i = tid; i < K3; i += 256) wsh[i] = wl[i];
-  }
+  // per-level weights: the address is uniform across the workgroup, so the
+  // tap loop reads them through scalar loads
+  using cfloat = const __attribute__((address_space(4))) float;   // read-only for the whole launch
+  cfloat* wl = (cfloat*)(uintptr_t)(INDEX ? a.w : a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * K3);
   const PT pad = INDEX ? PT(-1) : PT(0);
   for (int i = tid; i < NH * PY; i += 256) (&patch[0][0])[i] = pad;
   for (int s = tid; s < NSRC; s += 256) {
@@ -111,6 +183,7 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
     }
     sp[s] = b;
     se[s] = e;
+    scons[s] = 0;
   }
   for (int c = tid; c < NC; c += 256) {
     uint32_t b = 0, e = 0;
@@ -118,120 +191,124 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
     if (z < Dz && x < Dx) row_range(a.pend, m.prow[l] + uint32_t(z) * Dx + x, b, e);
     op[c] = b;
     oe[c] = e;
-  }
-  if (tid == 0) {
-    s_y0[0] = s_y0[1] = int(kNoY);
-    s_n[0] = s_n[1] = 0;
-    s_ymax[0] = s_ymax[1] = -1;
+    ocnt[c] = 0;
+    rymax[c] = -1;
+    rnext[c] = int(kNoY);
   }
   __syncthreads();
-  for (int c = tid; c < NC; c += 256)
-    if (op[c] < oe[c]) atomicMin(&s_y0[0], int(a.py[op[c]]));
+  if (wave == 0) {
+    int yf0 = int(kNoY);
+    if (lane < uint32_t(NC) && op[lane] < oe[lane]) yf0 = int(py[op[lane]]);
+    for (int o = 32; o > 0; o >>= 1) yf0 = min(yf0, __shfl_xor(yf0, o, 64));
+    if (lane == 0) s_y0 = yf0;
+    centre_caps_rows<NC, OCAP>(op, oe, opre, crow);
+  }
   __syncthreads();
 
-  int par = 0;
   while (true) {
-    const int y0 = s_y0[par];
+    const int y0 = s_y0;
     if (y0 == int(kNoY)) break;
+    const uint32_t nb = opre[NC];
 
-    // ---- B: list the outputs of this chunk
-    for (int c = wave; c < NC; c += 4) {
-      uint32_t base = op[c];
-      const uint32_t end = oe[c];
-      if (base >= end) continue;
-      int ymx = -1, ynext = int(kNoY);
-      while (true) {
-        const uint32_t i = base + lane;
-        const bool v = i < end;
-        const int yv = v ? int(a.py[i]) : kBig;
-        const bool in = v && yv < y0 + kYC;
-        const uint64_t mk = ballot(in);
-        const uint32_t cnt = __popcll(mk);
-        if (cnt) {
-          int slot0 = 0;
-          if (lane == 0) slot0 = atomicAdd(&s_n[par], int(cnt));
-          slot0 = __shfl(slot0, 0, 64);
-          if (in) {
-            const int q = slot0 + int(mask_rank(mk));
-            o_idx[q] = i;
-            o_pos[q] = uint16_t((c << 7) | (yv - y0 + R));
-          }
-          ymx = __shfl(yv, int(cnt) - 1, 64);
-        }
-        if (cnt == 64 && base + 64 < end) {
-          base += 64;
-          continue;
-        }
-        const int nxt = __shfl(yv, int(cnt & 63), 64);
-        base += cnt;
-        ynext = (base < end) ? nxt : int(kNoY);
-        break;
+    // ---- B (one memory round): list the outputs of this chunk -- every
+    // centre-row element from the row pointer on, up to OCAP of them (the
+    // (kYC+1)-th cannot lie in [y0, y0 + kYC) and so yields the row's next
+    // y) -- and fetch the y at every source-row pointer
+    int yf = kBig;
+    if (tid < NSRC && sp[tid] < se[tid])
+      yf = (tid >= NH && tid < 2 * NH) ? int(ty[sp[tid]]) : int(py[sp[tid]]);
+    for (uint32_t base = tid; base < nb; base += 256 * kBatch) {
+      // the listed elements of a row are a prefix of its items: the last of
+      // them (or the first item, when none is listed) records the row's
+      // count, last y and next y -- one writer per row, no atomics
+      int cc[kBatch], yv[kBatch], yn[kBatch];
+      uint32_t ii[kBatch], jj[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const uint32_t it = base + u * 256;
+        cc[u] = (it < nb) ? int(crow[it]) : 0;
+        jj[u] = (it < nb) ? it - opre[cc[u]] : 0u;
+        ii[u] = op[cc[u]] + jj[u];
       }
-      if (lane == 0) {
-        op[c] = base;
-        if (ynext != int(kNoY)) atomicMin(&s_y0[par ^ 1], ynext);
-        if (ymx >= 0) atomicMax(&s_ymax[par], ymx);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const bool ok = base + u * 256 < nb;
+        yv[u] = ok ? int(py[ii[u]]) : 0;
+        yn[u] = (ok && ii[u] + 1 < oe[cc[u]]) ? int(py[ii[u] + 1]) : int(kNoY);
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const uint32_t it = base + u * 256;
+        if (it >= nb) continue;
+        const int c = cc[u];
+        if (yv[u] < y0 + kYC) {
+          o_idx[it] = ii[u];
+          o_pos[it] = uint16_t((c << 7) | (yv[u] - y0 + R));
+          if (yn[u] >= y0 + kYC) {
+            ocnt[c] = jj[u] + 1;
+            rymax[c] = yv[u];
+            rnext[c] = yn[u];
+          }
+        } else {
+          o_idx[it] = kNone;
+          if (jj[u] == 0) rnext[c] = yv[u];
+        }
       }
     }
+    if (tid < NSRC) yfirst[tid] = yf;
     __syncthreads();
-    const int nout = s_n[par];
-    const int ymax = s_ymax[par];
-    const int ynx = s_y0[par ^ 1];
-    const int wlo = y0 - R, whi = ymax + R;
+    int ymax_c = -1, ynx = int(kNoY);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      ymax_c = max(ymax_c, rymax[c]);
+      ynx = min(ynx, rnext[c]);
+    }
+    const int wlo = y0 - R, whi = ymax_c + R;
     const int drop = (ynx == int(kNoY)) ? whi + 1 : ynx - R;   // cells below `drop` are never needed again
 
-    // ---- C: reconstruct the level-l patch over [wlo, whi]
-    for (int s = wave; s < NSRC; s += 4) {
-      uint32_t base = sp[s];
-      const uint32_t end = se[s];
-      if (base >= end) continue;
-      const bool coarse = s >= 2 * NH;
-      const bool istree = s >= NH && !coarse;
-      const uint16_t* __restrict__ ys = istree ? a.ty : a.py;
-      uint32_t consumed = 0;
-      while (true) {
-        const uint32_t i = base + lane;
-        const bool v = i < end;
-        const int yv = v ? int(ys[i]) : kBig;
-        const int lo = coarse ? 2 * yv : yv;
-        const int hi = coarse ? 2 * yv + 1 : yv;
-        if (v && hi >= wlo && lo <= whi) {
-          PT val;
-          if constexpr (INDEX)
-            val = PT((int64_t(coarse ? 2 : (istree ? 3 : 1)) << 40) | int64_t(i));
-          else
-            val = to_f32<TX>(istree ? tv[i] : xv[i]);
-          if (!coarse) {
-            patch[s - (istree ? NH : 0)][yv - wlo] = val;
-          } else {
-            const int j = s - 2 * NH;
-            const int hz0 = 2 * (j / PX) + R - 2, hx0 = 2 * (j % PX) + R - 2;
-#pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-              for (int dx = 0; dx < 2; ++dx) {
-                const int hz = hz0 + dz, hx = hx0 + dx;
-                if (hz < 0 || hx < 0 || hz >= HZ || hx >= HX) continue;
-                // a coarse cell on the far edge of an odd-sized grid covers
-                // level-l cells outside the image: those stay zero padding
-                if (z0 - R + hz >= Dz || x0 - R + hx >= Dx) continue;
-                if (lo >= wlo) patch[hz * HX + hx][lo - wlo] = val;
-                if (hi <= whi && hi < Dy) patch[hz * HX + hx][hi - wlo] = val;
-              }
-          }
-        }
-        consumed += __popcll(ballot(v && hi < drop));
-        const bool v63 = base + 63 < end;
-        const int lo63 = __shfl(lo, 63, 64), hi63 = __shfl(hi, 63, 64);
-        if (v63 && (lo63 <= whi || hi63 < drop)) {
-          base += 64;
-          continue;
-        }
-        break;
+    // ---- C0 (no memory round): wave 0 advances the centre pointers, lists
+    // the next chunk's centre caps, and sizes every source row's share of
+    // this window (y grows by >= 1 per element; a coarse element covers two
+    // cells); the other waves pad y outside the image
+    if (wave == 0) {
+      if (lane < uint32_t(NC)) {
+        op[lane] += ocnt[lane];
+        ocnt[lane] = 0;
       }
-      if (lane == 0) sp[s] += consumed;
+      centre_caps_rows<NC, OCAP>(op, oe, opre, crow);
+      const int b3 = int(lane) * 3;
+      uint32_t cap3[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int sr = b3 + q;
+        uint32_t cap = 0;
+        if (sr < NSRC && sp[sr] < se[sr]) {
+          const int last = (sr >= 2 * NH) ? (whi >> 1) : whi;
+          const int yfs = yfirst[sr];
+          cap = (last >= yfs) ? min(uint32_t(last - yfs + 1), se[sr] - sp[sr]) : 0u;
+        }
+        cap3[q] = cap;
+      }
+      const uint32_t sum = cap3[0] + cap3[1] + cap3[2];
+      uint32_t incl = sum;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t tt = __shfl_up(incl, o, 64);
+        if (lane >= uint32_t(o)) incl += tt;
+      }
+      const uint32_t ex = incl - sum;
+      if (b3 < NSRC) spre[b3] = ex;
+      if (b3 + 1 < NSRC) spre[b3 + 1] = ex + cap3[0];
+      if (b3 + 2 < NSRC) spre[b3 + 2] = ex + cap3[0] + cap3[1];
+      if (lane == 63) spre[NSRC] = incl;
     }
-    if (wlo < 0 || whi >= Dy) {
+    __syncthreads();
+    // source row of every patch item (items past kRowIdCap search instead)
+    for (int r = wave; r < NSRC; r += 4) {
+      const uint32_t b = spre[r], e = min(spre[r + 1], uint32_t(kRowIdCap));
+      for (uint32_t j = b + lane; j < e; j += 64) srow[j] = uint8_t(r);
+    }
+    if (wlo < 0 || whi >= Dy) {   // y outside the image is zero padding
       const int span = whi - wlo + 1;
       for (int j = tid; j < NH * span; j += 256) {
         const int h = j / span, p = j % span;
@@ -241,15 +318,84 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
     }
     __syncthreads();
 
-    // ---- D: accumulate the taps of every listed particle
-    if (tid == 0) {
-      s_y0[par] = int(kNoY);
-      s_n[par] = 0;
-      s_ymax[par] = -1;
+    // ---- C (one memory round): reconstruct the level-l patch over
+    // [wlo, whi], one element per thread across all source rows; values are
+    // fetched together with y, before knowing whether they fall in the window
+    const uint32_t ns = spre[NSRC];
+    for (uint32_t base = tid; base < ns; base += 256 * kBatch) {
+      int ss[kBatch], yv[kBatch], yn[kBatch];
+      uint32_t ii[kBatch], jj[kBatch];
+      PT val[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const uint32_t it = base + u * 256;
+        ss[u] = (it < ns) ? (it < uint32_t(kRowIdCap) ? int(srow[it]) : find_row(spre, NSRC, it)) : 0;
+        jj[u] = (it < ns) ? it - spre[ss[u]] : 0u;
+        ii[u] = sp[ss[u]] + jj[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const bool ok = base + u * 256 < ns;
+        const bool istree = ss[u] >= NH && ss[u] < 2 * NH;
+        yv[u] = ok ? (istree ? int(ty[ii[u]]) : int(py[ii[u]])) : kBig;
+        // next element of the row, if it is one of this chunk's items
+        const bool has_next = ok && jj[u] + 1 < spre[ss[u] + 1] - spre[ss[u]];
+        yn[u] = has_next ? (istree ? int(ty[ii[u] + 1]) : int(py[ii[u] + 1])) : kBig;
+        if constexpr (INDEX)
+          val[u] = PT((int64_t(ss[u] >= 2 * NH ? 2 : (istree ? 3 : 1)) << 40) | int64_t(ii[u]));
+        else
+          val[u] = ok ? to_f32<TX>(istree ? tv[ii[u]] : xv[ii[u]]) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        if (base + u * 256 >= ns) continue;
+        const int s = ss[u];
+        const bool coarse = s >= 2 * NH;
+        const bool istree = s >= NH && !coarse;
+        const int lo = coarse ? 2 * yv[u] : yv[u];
+        const int hi = coarse ? 2 * yv[u] + 1 : yv[u];
+        if (hi >= wlo && lo <= whi) {
+          if (!coarse) {
+            patch[s - (istree ? NH : 0)][yv[u] - wlo] = val[u];
+          } else {
+            const int js = s - 2 * NH;
+            const int hz0 = 2 * (js / PX) + R - 2, hx0 = 2 * (js % PX) + R - 2;
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+              for (int dx = 0; dx < 2; ++dx) {
+                const int hz = hz0 + dz, hx = hx0 + dx;
+                if (hz < 0 || hx < 0 || hz >= HZ || hx >= HX) continue;
+                // a coarse cell on the far edge of an odd-sized grid covers
+                // level-l cells outside the image: those stay zero padding
+                if (z0 - R + hz >= Dz || x0 - R + hx >= Dx) continue;
+                if (lo >= wlo) patch[hz * HX + hx][lo - wlo] = val[u];
+                if (hi <= whi && hi < Dy) patch[hz * HX + hx][hi - wlo] = val[u];
+              }
+          }
+        }
+        // consumed elements are a prefix of the row's items: the last one
+        // records the count
+        const int hin = coarse ? 2 * yn[u] + 1 : yn[u];
+        if (hi < drop && !(hin < drop)) scons[s] = jj[u] + 1;
+      }
     }
-    for (int j = tid; j < nout; j += 256) {
-      const uint32_t idx = o_idx[j];
-      const int pos = o_pos[j];
+    __syncthreads();
+
+    // ---- D: accumulate the taps of every listed particle
+    for (int s = tid; s < NSRC; s += 256) {
+      sp[s] += scons[s];
+      scons[s] = 0;
+    }
+    if (tid == 0) s_y0 = ynx;
+    if (tid < NC) {   // every thread has read them before the last barrier
+      rymax[tid] = -1;
+      rnext[tid] = int(kNoY);
+    }
+    for (uint32_t jt = tid; jt < nb; jt += 256) {
+      const uint32_t idx = o_idx[jt];
+      if (idx == kNone) continue;
+      const int pos = o_pos[jt];
       const int c = pos >> 7, p0 = pos & 127;
       const int hz = c / kTileX, hx = c % kTileX;   // halo row of the tap (-R,-R) is (hz, hx)
       if constexpr (INDEX) {
@@ -268,15 +414,16 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
         }
       } else {
         float acc = 0.f;
-        int q = 0;
-#pragma unroll
-        for (int dz = 0; dz < K; ++dz)
+#pragma unroll 1
+        for (int dz = 0; dz < K; ++dz) {
+          cfloat* wz = wl + dz * K * K;
 #pragma unroll
           for (int dx = 0; dx < K; ++dx) {
             const float* row = &patch[(hz + dz) * HX + hx + dx][p0 - R];
 #pragma unroll
-            for (int dy = 0; dy < K; ++dy) acc = fmaf(wsh[q++], row[dy], acc);
+            for (int dy = 0; dy < K; ++dy) acc = fmaf(wz[dx * K + dy], row[dy], acc);
           }
+        }
         TY* yo = static_cast<TY*>(a.y);
         if (a.epi == APR_EPI_RATIO) {
           const float u = to_f32<TY>(static_cast<const TY*>(a.epi_arg)[idx]);
@@ -288,7 +435,6 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
       }
     }
     __syncthreads();
-    par ^= 1;
   }
 }
 
