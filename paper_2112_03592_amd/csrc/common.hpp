@@ -33,8 +33,8 @@ __host__ __device__ inline void tile_unpack(uint64_t t, int& l, int& tz, int& tx
   tx = int(t & 0xffffffu);
 }
 
-constexpr int kTileZ = 4;   // output rows per tile along z
-constexpr int kTileX = 4;   // output rows per tile along x
+constexpr int kTileZ = 8;   // output rows per tile along z
+constexpr int kTileX = 8;   // output rows per tile along x
 
 // ---------------------------------------------------------------------------
 // Device helpers

@@ -1,23 +1,25 @@
 // Single-channel APR convolution (Section 4.1), GPU design after Section 5.2,
 // re-shaped for wave64 / CDNA4.
 //
-// Work item: one tile of 4 x 4 particle rows (z, x) at one level l, taken from
-// the non-empty tile list.  The workgroup (4 waves) sweeps the tile along y in
-// chunks: each chunk starts at the smallest unprocessed y of the tile's output
-// particles (empty stretches of the rows are skipped) and covers at most 64
-// cells.  Per chunk:
-//   B. the output particles of the 16 centre rows with y in [y0, y0+64) are
-//      listed in LDS (ballot + rank per wave, one shared counter);
-//   C. the level-l patch of the halo rows is reconstructed in LDS over
-//      [y0 - r, ymax + r] from three sorted sources, streamed with running
-//      pointers and coalesced lane-per-element loads: APR level l, tree level
-//      l (cells containing finer particles), APR level l-1 (each element
-//      covers 2 x 2 x 2 level-l cells).  With 26-neighbour 2:1 balance these
-//      sources cover every cell within radius 2 of a level-l particle;
+// Work item: one tile of kTileZ x kTileX particle rows (z, x) at one level l,
+// from the non-empty tile list (the pre-pass of Section 5.2).  A workgroup of
+// 512 threads sweeps its tile along y in chunks; each chunk starts at the
+// smallest unprocessed y of the tile's output particles (empty stretches are
+// skipped) and spans at most kYC cells.  Per chunk:
+//   B. list the output particles of the centre rows that fall in
+//      [y0, y0 + kYC), and fetch the y at every source-row pointer;
+//   C. reconstruct the level-l patch of the halo rows in LDS over
+//      [y0 - r, ymax + r] from three sorted sources -- APR level l, tree level
+//      l (cells containing finer particles), APR level l-1 (each element covers
+//      2 x 2 x 2 level-l cells).  With 26-neighbour 2:1 balance these cover
+//      every cell within radius 2 of a level-l particle.  Elements of all
+//      source rows are spread flat over the threads (coalesced within a row),
+//      y and value fetched in one memory round;
 //   D. every listed particle accumulates its k^3 taps from the patch in FP32
-//      and writes its output.
-// The blockIdx -> tile map gives each XCD a contiguous run of tiles so that
-// halo rows shared by neighbouring tiles are re-read from the same L2.
+//      (weights in scalar registers) and writes its output.
+// Per-row bookkeeping uses one writer per row (the last element of a prefix),
+// no atomics.  The blockIdx -> tile map gives each XCD a contiguous run of
+// tiles so that halo rows shared by neighbouring tiles hit the same L2.
 #include <type_traits>
 
 #include "common.hpp"
@@ -25,9 +27,10 @@
 namespace apr {
 
 constexpr int kYC = 64;          // output cells per chunk along y
-constexpr int kBig = 1 << 28;    // y of a lane past the end of its row
+constexpr int kBig = 1 << 28;    // y of an element past the end of its row
 constexpr int kBatch = 4;        // independent elements per thread in flight
-constexpr int kRowIdCap = 4096;  // patch items per chunk with a stored source row
+constexpr int kRowIdCap = 3584;  // patch items per chunk with a stored source row
+constexpr int kConvThreads = 512;
 
 struct ConvArgs {
   Meta m;
@@ -50,23 +53,32 @@ struct ConvArgs {
   int64_t* map;         // neighbour-map mode output [n_sel][k^3]
 };
 
-// exclusive scan of n <= 192 LDS entries in place by one wave; data[n] = total
-__device__ inline void wave_scan_lds(uint32_t* data, int n) {
+// exclusive scan of n LDS entries in place by one wave (E entries per lane,
+// n <= 64 * E); data[n] = total.  `fill(k)` yields the value of entry k.
+template <int E, typename F>
+__device__ inline void wave_scan_into(uint32_t* data, int n, F fill) {
   const uint32_t lane = lane_id();
-  const int b = int(lane) * 3;
-  uint32_t v0 = (b < n) ? data[b] : 0u, v1 = (b + 1 < n) ? data[b + 1] : 0u,
-           v2 = (b + 2 < n) ? data[b + 2] : 0u;
-  const uint32_t s = v0 + v1 + v2;
-  uint32_t incl = s;
+  uint32_t v[E];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int k = int(lane) * E + q;
+    v[q] = (k < n) ? fill(k) : 0u;
+    sum += v[q];
+  }
+  uint32_t incl = sum;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t t = __shfl_up(incl, o, 64);
     if (lane >= uint32_t(o)) incl += t;
   }
-  const uint32_t ex = incl - s;
-  if (b < n) data[b] = ex;
-  if (b + 1 < n) data[b + 1] = ex + v0;
-  if (b + 2 < n) data[b + 2] = ex + v0 + v1;
+  uint32_t run = incl - sum;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int k = int(lane) * E + q;
+    if (k < n) data[k] = run;
+    run += v[q];
+  }
   if (lane == 63) data[n] = incl;
 }
 
@@ -80,60 +92,38 @@ __device__ inline int find_row(const uint32_t* pre, int n, uint32_t v) {
   return lo;
 }
 
-// wave 0: opre[c] = exclusive prefix of min(oe[c] - op[c], OCAP), opre[NC] = total
-template <int NC, int OCAP>
-__device__ inline void centre_caps(const uint32_t* op, const uint32_t* oe, uint32_t* opre) {
-  const uint32_t lane = lane_id();
-  const uint32_t cap = (lane < uint32_t(NC)) ? min(oe[lane] - op[lane], uint32_t(OCAP)) : 0u;
-  uint32_t incl = cap;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t tt = __shfl_up(incl, o, 64);
-    if (lane >= uint32_t(o)) incl += tt;
-  }
-  if (lane < uint32_t(NC)) opre[lane] = incl - cap;
-  if (lane == uint32_t(NC - 1)) opre[NC] = incl;
-}
-
-// wave 0: centre caps as above, then crow[item] = centre row of each item
-template <int NC, int OCAP>
-__device__ inline void centre_caps_rows(const uint32_t* op, const uint32_t* oe, uint32_t* opre,
-                                        uint8_t* crow) {
-  centre_caps<NC, OCAP>(op, oe, opre);
-  wave_lds_sync();
-  const uint32_t lane = lane_id();
-  for (int c = 0; c < NC; ++c) {
-    const uint32_t b = opre[c], n = opre[c + 1] - b;
-    for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
-  }
-}
-
 template <int K, typename TX, typename TY, bool INDEX>
-__global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
+__global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
+  constexpr int NT = kConvThreads, NW = NT / 64;
   constexpr int R = K / 2;
-  constexpr int HZ = kTileZ + 2 * R, HX = kTileX + 2 * R;
+  constexpr int TZ = kTileZ, TX_ = kTileX;
+  constexpr int HZ = TZ + 2 * R, HX = TX_ + 2 * R;
   constexpr int NH = HZ * HX;                        // halo rows at level l
-  constexpr int PZ = ((kTileZ - 1 + R) >> 1) + 2;    // parent rows (level l-1)
-  constexpr int PX = ((kTileX - 1 + R) >> 1) + 2;
-  constexpr int NSRC = 2 * NH + PZ * PX;             // [0,NH) APR l, [NH,2NH) tree l, rest APR l-1
-  constexpr int NC = kTileZ * kTileX;                // centre (output) rows
+  constexpr int PZ = ((TZ - 1 + R) >> 1) + 2;        // parent rows (level l-1)
+  constexpr int PX = ((TX_ - 1 + R) >> 1) + 2;
+  constexpr int NCR = PZ * PX;
+  constexpr int NSRC = 2 * NH + NCR;                 // [0,NH) APR l, [NH,2NH) tree l, rest APR l-1
+  constexpr int NC = TZ * TX_;                       // centre (output) rows
   constexpr int PY = kYC + 2 * R;
   constexpr int K3 = K * K * K;
   constexpr int OCAP = kYC + 1;                      // centre-row elements examined per chunk
-  constexpr uint32_t kNone = 0xffffffffu;
+  constexpr int NOUT = NC * OCAP;
+  constexpr int ES = (NSRC + 63) / 64;               // scan entries per lane
+  constexpr uint16_t kUnlisted = 0xffffu;
   using PT = typename std::conditional<INDEX, long long, float>::type;
-  static_assert(PY <= 128, "patch position packs into 7 bits");
-  static_assert(NSRC <= 192 && NC <= 64, "scan sizes");
+  static_assert(NC <= 64 && kYC == 64, "centre rows and offsets pack into 16 bits");
+  static_assert(NSRC < 65536 && NT >= NSRC, "one thread per source row");
 
-  __shared__ PT patch[NH][PY];
+  __shared__ PT patch[NH * PY];
   __shared__ uint32_t sp[NSRC], se[NSRC], spre[NSRC + 1], scons[NSRC];
   __shared__ int yfirst[NSRC];
-  __shared__ uint32_t op[NC], oe[NC], opre[NC + 1], ocnt[NC];
-  __shared__ int rymax[NC], rnext[NC];     // per centre row: last listed y, next y
-  __shared__ uint32_t o_idx[NC * OCAP];
-  __shared__ uint16_t o_pos[NC * OCAP];
-  __shared__ uint8_t crow[NC * OCAP];      // centre row of each listing item
-  __shared__ uint8_t srow[kRowIdCap];      // source row of each patch item
+  __shared__ uint8_t cmask[NCR];            // coarse row -> valid target halo rows (bit q: dz = q/2, dx = q%2)
+  __shared__ int16_t cbase[NCR];            // coarse row -> halo row of target q = 0
+  __shared__ uint32_t op[NC], oe[NC], opd[NC], ocnt[NC], opre[2][NC + 1];
+  __shared__ int rymax[NC], rnext[NC];      // per centre row: last listed y, next y
+  __shared__ uint8_t crow[NOUT];            // centre row of each listing item
+  __shared__ uint16_t o_pos[NOUT];          // (centre row << 6) | (y - y0), or kUnlisted
+  __shared__ uint16_t srow[kRowIdCap];      // source row of each patch item
   __shared__ int s_y0;
 
   const int tid = threadIdx.x;
@@ -152,7 +142,7 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
   tz = __builtin_amdgcn_readfirstlane(tz);
   tx = __builtin_amdgcn_readfirstlane(tx);
   const Meta& m = a.m;
-  const int z0 = tz * kTileZ, x0 = tx * kTileX;
+  const int z0 = tz * TZ, x0 = tx * TX_;
   const int Dz = m.dz[l], Dx = m.dx[l], Dy = m.dy[l];
   const bool has_c = l > m.l_min;
   const bool has_t = l <= m.t_hi;
@@ -160,14 +150,15 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
   const TX* __restrict__ tv = static_cast<const TX*>(a.tree);
   const uint16_t* __restrict__ py = a.py;
   const uint16_t* __restrict__ ty = a.ty;
-
-  // per-level weights: the address is uniform across the workgroup, so the
-  // tap loop reads them through scalar loads
-  using cfloat = const __attribute__((address_space(4))) float;   // read-only for the whole launch
+  // per-level weights: read-only for the whole launch and uniform across the
+  // workgroup, so the tap loop reads them through scalar loads
+  using cfloat = const __attribute__((address_space(4))) float;
   cfloat* wl = (cfloat*)(uintptr_t)(INDEX ? a.w : a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * K3);
+
+  // ---- setup
   const PT pad = INDEX ? PT(-1) : PT(0);
-  for (int i = tid; i < NH * PY; i += 256) (&patch[0][0])[i] = pad;
-  for (int s = tid; s < NSRC; s += 256) {
+  for (int i = tid; i < NH * PY; i += NT) patch[i] = pad;
+  for (int s = tid; s < NSRC; s += NT) {
     uint32_t b = 0, e = 0;
     if (s < 2 * NH) {
       const int h = s < NH ? s : s - NH;
@@ -175,19 +166,33 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
       const bool in = z >= 0 && x >= 0 && z < Dz && x < Dx;
       if (in && s < NH) row_range(a.pend, m.prow[l] + uint32_t(z) * Dx + x, b, e);
       if (in && s >= NH && has_t) row_range(a.tend, m.trow[l] + uint32_t(z) * Dx + x, b, e);
-    } else if (has_c) {
+    } else {
+      // the coarse element of parent row j covers halo rows
+      // hz = 2 * (j / PX) + R - 2 + {0, 1}, hx likewise; a halo row is a
+      // target if it lies in the halo and in the level-l grid (a coarse cell
+      // on the far edge of an odd-sized grid covers cells outside the image,
+      // which stay zero padding)
       const int j = s - 2 * NH;
       const int pz = z0 / 2 - 1 + j / PX, px = x0 / 2 - 1 + j % PX;
-      if (pz >= 0 && px >= 0 && pz < m.dz[l - 1] && px < m.dx[l - 1])
+      if (has_c && pz >= 0 && px >= 0 && pz < m.dz[l - 1] && px < m.dx[l - 1])
         row_range(a.pend, m.prow[l - 1] + uint32_t(pz) * m.dx[l - 1] + px, b, e);
+      const int hz0 = 2 * (j / PX) + R - 2, hx0 = 2 * (j % PX) + R - 2;
+      int msk = 0;
+      for (int q = 0; q < 4; ++q) {
+        const int hz = hz0 + (q >> 1), hx = hx0 + (q & 1);
+        if (hz >= 0 && hx >= 0 && hz < HZ && hx < HX && z0 - R + hz < Dz && x0 - R + hx < Dx)
+          msk |= 1 << q;
+      }
+      cmask[j] = uint8_t(msk);
+      cbase[j] = int16_t(hz0 * HX + hx0);
     }
     sp[s] = b;
     se[s] = e;
     scons[s] = 0;
   }
-  for (int c = tid; c < NC; c += 256) {
+  for (int c = tid; c < NC; c += NT) {
     uint32_t b = 0, e = 0;
-    const int z = z0 + c / kTileX, x = x0 + c % kTileX;
+    const int z = z0 + c / TX_, x = x0 + c % TX_;
     if (z < Dz && x < Dx) row_range(a.pend, m.prow[l] + uint32_t(z) * Dx + x, b, e);
     op[c] = b;
     oe[c] = e;
@@ -201,203 +206,207 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
     if (lane < uint32_t(NC) && op[lane] < oe[lane]) yf0 = int(py[op[lane]]);
     for (int o = 32; o > 0; o >>= 1) yf0 = min(yf0, __shfl_xor(yf0, o, 64));
     if (lane == 0) s_y0 = yf0;
-    centre_caps_rows<NC, OCAP>(op, oe, opre, crow);
+    wave_scan_into<1>(opre[0], NC, [&](int c) { return min(oe[c] - op[c], uint32_t(OCAP)); });
+    wave_lds_sync();
+    for (int c = 0; c < NC; ++c) {
+      const uint32_t b = opre[0][c], n = opre[0][c + 1] - b;
+      for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
+    }
   }
   __syncthreads();
 
+  int par = 0;
   while (true) {
     const int y0 = s_y0;
     if (y0 == int(kNoY)) break;
-    const uint32_t nb = opre[NC];
+    const uint32_t* ocap = opre[par];
+    const uint32_t nb = ocap[NC];
 
-    // ---- B (one memory round): list the outputs of this chunk -- every
-    // centre-row element from the row pointer on, up to OCAP of them (the
-    // (kYC+1)-th cannot lie in [y0, y0 + kYC) and so yields the row's next
-    // y) -- and fetch the y at every source-row pointer
+    // ---- B (one memory round): the listed elements of a centre row are a
+    // prefix of its items; the last of them (or the first item, when none is
+    // listed) records the row's count, last y and next y.  Also fetch the y
+    // at every source-row pointer.
     int yf = kBig;
-    if (tid < NSRC && sp[tid] < se[tid])
-      yf = (tid >= NH && tid < 2 * NH) ? int(ty[sp[tid]]) : int(py[sp[tid]]);
-    for (uint32_t base = tid; base < nb; base += 256 * kBatch) {
-      // the listed elements of a row are a prefix of its items: the last of
-      // them (or the first item, when none is listed) records the row's
-      // count, last y and next y -- one writer per row, no atomics
+    if (tid < NSRC && sp[tid] < se[tid]) yf = (tid >= NH && tid < 2 * NH) ? int(ty[sp[tid]]) : int(py[sp[tid]]);
+    for (uint32_t base = tid; base < nb; base += NT * kBatch) {
       int cc[kBatch], yv[kBatch], yn[kBatch];
       uint32_t ii[kBatch], jj[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const uint32_t it = base + u * 256;
-        cc[u] = (it < nb) ? int(crow[it]) : 0;
-        jj[u] = (it < nb) ? it - opre[cc[u]] : 0u;
+        const uint32_t it = base + u * NT;
+        const bool ok = it < nb;
+        cc[u] = ok ? int(crow[it]) : 0;
+        jj[u] = ok ? it - ocap[cc[u]] : 0u;
         ii[u] = op[cc[u]] + jj[u];
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const bool ok = base + u * 256 < nb;
         yv[u] = ok ? int(py[ii[u]]) : 0;
         yn[u] = (ok && ii[u] + 1 < oe[cc[u]]) ? int(py[ii[u] + 1]) : int(kNoY);
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const uint32_t it = base + u * 256;
+        const uint32_t it = base + u * NT;
         if (it >= nb) continue;
         const int c = cc[u];
         if (yv[u] < y0 + kYC) {
-          o_idx[it] = ii[u];
-          o_pos[it] = uint16_t((c << 7) | (yv[u] - y0 + R));
+          o_pos[it] = uint16_t((c << 6) | (yv[u] - y0));
           if (yn[u] >= y0 + kYC) {
             ocnt[c] = jj[u] + 1;
             rymax[c] = yv[u];
             rnext[c] = yn[u];
           }
         } else {
-          o_idx[it] = kNone;
+          o_pos[it] = kUnlisted;
           if (jj[u] == 0) rnext[c] = yv[u];
         }
       }
     }
     if (tid < NSRC) yfirst[tid] = yf;
     __syncthreads();
-    int ymax_c = -1, ynx = int(kNoY);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      ymax_c = max(ymax_c, rymax[c]);
-      ynx = min(ynx, rnext[c]);
+    // every wave reduces the per-row results itself (no extra barrier)
+    int ymax_c = (lane < uint32_t(NC)) ? rymax[lane] : -1;
+    int ynx = (lane < uint32_t(NC)) ? rnext[lane] : int(kNoY);
+    for (int o = 32; o > 0; o >>= 1) {
+      ymax_c = max(ymax_c, __shfl_xor(ymax_c, o, 64));
+      ynx = min(ynx, __shfl_xor(ynx, o, 64));
     }
     const int wlo = y0 - R, whi = ymax_c + R;
     const int drop = (ynx == int(kNoY)) ? whi + 1 : ynx - R;   // cells below `drop` are never needed again
 
-    // ---- C0 (no memory round): wave 0 advances the centre pointers, lists
-    // the next chunk's centre caps, and sizes every source row's share of
+    // ---- C0 (no memory round): wave 0 advances the centre pointers, sizes
+    // the next chunk's centre items, and sizes every source row's share of
     // this window (y grows by >= 1 per element; a coarse element covers two
     // cells); the other waves pad y outside the image
     if (wave == 0) {
       if (lane < uint32_t(NC)) {
+        opd[lane] = op[lane];
         op[lane] += ocnt[lane];
         ocnt[lane] = 0;
       }
-      centre_caps_rows<NC, OCAP>(op, oe, opre, crow);
-      const int b3 = int(lane) * 3;
-      uint32_t cap3[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int sr = b3 + q;
-        uint32_t cap = 0;
-        if (sr < NSRC && sp[sr] < se[sr]) {
-          const int last = (sr >= 2 * NH) ? (whi >> 1) : whi;
-          const int yfs = yfirst[sr];
-          cap = (last >= yfs) ? min(uint32_t(last - yfs + 1), se[sr] - sp[sr]) : 0u;
-        }
-        cap3[q] = cap;
-      }
-      const uint32_t sum = cap3[0] + cap3[1] + cap3[2];
-      uint32_t incl = sum;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t tt = __shfl_up(incl, o, 64);
-        if (lane >= uint32_t(o)) incl += tt;
-      }
-      const uint32_t ex = incl - sum;
-      if (b3 < NSRC) spre[b3] = ex;
-      if (b3 + 1 < NSRC) spre[b3 + 1] = ex + cap3[0];
-      if (b3 + 2 < NSRC) spre[b3 + 2] = ex + cap3[0] + cap3[1];
-      if (lane == 63) spre[NSRC] = incl;
-    }
-    __syncthreads();
-    // source row of every patch item (items past kRowIdCap search instead)
-    for (int r = wave; r < NSRC; r += 4) {
-      const uint32_t b = spre[r], e = min(spre[r + 1], uint32_t(kRowIdCap));
-      for (uint32_t j = b + lane; j < e; j += 64) srow[j] = uint8_t(r);
-    }
-    if (wlo < 0 || whi >= Dy) {   // y outside the image is zero padding
+      wave_lds_sync();
+      wave_scan_into<1>(opre[par ^ 1], NC, [&](int c) { return min(oe[c] - op[c], uint32_t(OCAP)); });
+      wave_scan_into<ES>(spre, NSRC, [&](int sr) -> uint32_t {
+        if (sp[sr] >= se[sr]) return 0u;
+        const int last = (sr >= 2 * NH) ? (whi >> 1) : whi;
+        const int yfs = yfirst[sr];
+        return (last >= yfs) ? min(uint32_t(last - yfs + 1), se[sr] - sp[sr]) : 0u;
+      });
+    } else if (wlo < 0 || whi >= Dy) {   // y outside the image is zero padding
       const int span = whi - wlo + 1;
-      for (int j = tid; j < NH * span; j += 256) {
+      for (int j = tid - 64; j < NH * span; j += NT - 64) {
         const int h = j / span, p = j % span;
         const int yy = wlo + p;
-        if (yy < 0 || yy >= Dy) patch[h][p] = pad;
+        if (yy < 0 || yy >= Dy) patch[h * PY + p] = pad;
+      }
+    }
+    __syncthreads();
+    // source row of every patch item (items past kRowIdCap search instead);
+    // centre row of every next-chunk listing item
+    for (int r = wave; r < NSRC; r += NW) {
+      const uint32_t b = spre[r], e = min(spre[r + 1], uint32_t(kRowIdCap));
+      for (uint32_t j = b + lane; j < e; j += 64) srow[j] = uint16_t(r);
+    }
+    {
+      const uint32_t* nc = opre[par ^ 1];
+      for (int c = wave; c < NC; c += NW) {
+        const uint32_t b = nc[c], n = nc[c + 1] - b;
+        for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
       }
     }
     __syncthreads();
 
-    // ---- C (one memory round): reconstruct the level-l patch over
-    // [wlo, whi], one element per thread across all source rows; values are
-    // fetched together with y, before knowing whether they fall in the window
+    // ---- C (one memory round): reconstruct the level-l patch over [wlo, whi]
     const uint32_t ns = spre[NSRC];
-    for (uint32_t base = tid; base < ns; base += 256 * kBatch) {
+    const uint32_t nsf = spre[2 * NH];   // items of APR-l and tree-l rows come first
+    // fine sources: one patch cell per element
+    for (uint32_t base = tid; base < nsf; base += NT * kBatch) {
       int ss[kBatch], yv[kBatch], yn[kBatch];
       uint32_t ii[kBatch], jj[kBatch];
       PT val[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const uint32_t it = base + u * 256;
-        ss[u] = (it < ns) ? (it < uint32_t(kRowIdCap) ? int(srow[it]) : find_row(spre, NSRC, it)) : 0;
-        jj[u] = (it < ns) ? it - spre[ss[u]] : 0u;
+        const uint32_t it = base + u * NT;
+        const bool ok = it < nsf;
+        ss[u] = ok ? (it < uint32_t(kRowIdCap) ? int(srow[it]) : find_row(spre, NSRC, it)) : 0;
+        jj[u] = ok ? it - spre[ss[u]] : 0u;
         ii[u] = sp[ss[u]] + jj[u];
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const bool ok = base + u * 256 < ns;
-        const bool istree = ss[u] >= NH && ss[u] < 2 * NH;
-        yv[u] = ok ? (istree ? int(ty[ii[u]]) : int(py[ii[u]])) : kBig;
+        const bool istree = ss[u] >= NH;
+        const uint16_t* ys = istree ? ty : py;
+        yv[u] = ok ? int(ys[ii[u]]) : kBig;
         // next element of the row, if it is one of this chunk's items
         const bool has_next = ok && jj[u] + 1 < spre[ss[u] + 1] - spre[ss[u]];
-        yn[u] = has_next ? (istree ? int(ty[ii[u] + 1]) : int(py[ii[u] + 1])) : kBig;
+        yn[u] = has_next ? int(ys[ii[u] + 1]) : kBig;
         if constexpr (INDEX)
-          val[u] = PT((int64_t(ss[u] >= 2 * NH ? 2 : (istree ? 3 : 1)) << 40) | int64_t(ii[u]));
+          val[u] = PT((int64_t(istree ? 3 : 1) << 40) | int64_t(ii[u]));
         else
-          val[u] = ok ? to_f32<TX>(istree ? tv[ii[u]] : xv[ii[u]]) : 0.f;
+          val[u] = ok ? to_f32<TX>((istree ? tv : xv)[ii[u]]) : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        if (base + u * 256 >= ns) continue;
+        if (base + u * NT >= nsf) continue;
         const int s = ss[u];
-        const bool coarse = s >= 2 * NH;
-        const bool istree = s >= NH && !coarse;
-        const int lo = coarse ? 2 * yv[u] : yv[u];
-        const int hi = coarse ? 2 * yv[u] + 1 : yv[u];
-        if (hi >= wlo && lo <= whi) {
-          if (!coarse) {
-            patch[s - (istree ? NH : 0)][yv[u] - wlo] = val[u];
-          } else {
-            const int js = s - 2 * NH;
-            const int hz0 = 2 * (js / PX) + R - 2, hx0 = 2 * (js % PX) + R - 2;
-#pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-              for (int dx = 0; dx < 2; ++dx) {
-                const int hz = hz0 + dz, hx = hx0 + dx;
-                if (hz < 0 || hx < 0 || hz >= HZ || hx >= HX) continue;
-                // a coarse cell on the far edge of an odd-sized grid covers
-                // level-l cells outside the image: those stay zero padding
-                if (z0 - R + hz >= Dz || x0 - R + hx >= Dx) continue;
-                if (lo >= wlo) patch[hz * HX + hx][lo - wlo] = val[u];
-                if (hi <= whi && hi < Dy) patch[hz * HX + hx][hi - wlo] = val[u];
-              }
-          }
-        }
+        if (yv[u] >= wlo && yv[u] <= whi) patch[(s >= NH ? s - NH : s) * PY + (yv[u] - wlo)] = val[u];
         // consumed elements are a prefix of the row's items: the last one
         // records the count
-        const int hin = coarse ? 2 * yn[u] + 1 : yn[u];
-        if (hi < drop && !(hin < drop)) scons[s] = jj[u] + 1;
+        if (yv[u] < drop && !(yn[u] < drop)) scons[s] = jj[u] + 1;
+      }
+    }
+    // coarse sources (APR level l-1): each element covers 2 x 2 x 2 level-l
+    // cells, in up to four halo rows
+    for (uint32_t base = nsf + tid; base < ns; base += NT * kBatch) {
+      int ss[kBatch], yv[kBatch], yn[kBatch];
+      uint32_t ii[kBatch], jj[kBatch];
+      PT val[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const uint32_t it = base + u * NT;
+        const bool ok = it < ns;
+        ss[u] = ok ? (it < uint32_t(kRowIdCap) ? int(srow[it]) : find_row(spre, NSRC, it)) : 2 * NH;
+        jj[u] = ok ? it - spre[ss[u]] : 0u;
+        ii[u] = sp[ss[u]] + jj[u];
+        yv[u] = ok ? int(py[ii[u]]) : kBig;
+        const bool has_next = ok && jj[u] + 1 < spre[ss[u] + 1] - spre[ss[u]];
+        yn[u] = has_next ? int(py[ii[u] + 1]) : kBig;
+        if constexpr (INDEX)
+          val[u] = PT((int64_t(2) << 40) | int64_t(ii[u]));
+        else
+          val[u] = ok ? to_f32<TX>(xv[ii[u]]) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        if (base + u * NT >= ns) continue;
+        const int s = ss[u];
+        const int lo = 2 * yv[u];
+        const int js = s - 2 * NH;
+        const int msk = cmask[js], hb = cbase[js];
+        const bool w0 = lo >= wlo && lo <= whi;
+        const bool w1 = lo + 1 >= wlo && lo + 1 <= whi && lo + 1 < Dy;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!((msk >> q) & 1)) continue;
+          PT* row = patch + (hb + (q >> 1) * HX + (q & 1)) * PY - wlo;
+          if (w0) row[lo] = val[u];
+          if (w1) row[lo + 1] = val[u];
+        }
+        if (lo + 1 < drop && !(2 * yn[u] + 1 < drop)) scons[s] = jj[u] + 1;
       }
     }
     __syncthreads();
 
     // ---- D: accumulate the taps of every listed particle
-    for (int s = tid; s < NSRC; s += 256) {
+    for (int s = tid; s < NSRC; s += NT) {
       sp[s] += scons[s];
       scons[s] = 0;
     }
     if (tid == 0) s_y0 = ynx;
-    if (tid < NC) {   // every thread has read them before the last barrier
+    if (tid < NC) {   // every wave has read them before the last barrier
       rymax[tid] = -1;
       rnext[tid] = int(kNoY);
     }
-    for (uint32_t jt = tid; jt < nb; jt += 256) {
-      const uint32_t idx = o_idx[jt];
-      if (idx == kNone) continue;
+    for (uint32_t jt = tid; jt < nb; jt += NT) {
       const int pos = o_pos[jt];
-      const int c = pos >> 7, p0 = pos & 127;
-      const int hz = c / kTileX, hx = c % kTileX;   // halo row of the tap (-R,-R) is (hz, hx)
+      if (pos == kUnlisted) continue;
+      const int c = pos >> 6, p0 = (pos & 63) + R;
+      const uint32_t idx = opd[c] + (jt - ocap[c]);
+      const int hz = c / TX_, hx = c % TX_;   // halo row of the tap (-R, -R) is (hz, hx)
       if constexpr (INDEX) {
         int64_t lo = 0, hi = a.n_sel;
         while (lo < hi) {
@@ -410,7 +419,7 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
           for (int dz = 0; dz < K; ++dz)
             for (int dx = 0; dx < K; ++dx)
               for (int dy = 0; dy < K; ++dy)
-                dst[q++] = int64_t(patch[(hz + dz) * HX + hx + dx][p0 - R + dy]);
+                dst[q++] = int64_t(patch[((hz + dz) * HX + hx + dx) * PY + p0 - R + dy]);
         }
       } else {
         float acc = 0.f;
@@ -419,7 +428,7 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
           cfloat* wz = wl + dz * K * K;
 #pragma unroll
           for (int dx = 0; dx < K; ++dx) {
-            const float* row = &patch[(hz + dz) * HX + hx + dx][p0 - R];
+            const float* row = &patch[((hz + dz) * HX + hx + dx) * PY + p0 - R];
 #pragma unroll
             for (int dy = 0; dy < K; ++dy) acc = fmaf(wz[dx * K + dy], row[dy], acc);
           }
@@ -435,6 +444,7 @@ __global__ __launch_bounds__(256) void conv1_kernel(ConvArgs a) {
       }
     }
     __syncthreads();
+    par ^= 1;
   }
 }
 
@@ -443,12 +453,12 @@ static apr_status launch_conv(const ConvArgs& args, int xdt, int ydt, hipStream_
   const int64_t per = (args.n_tiles + 7) / 8;
   const dim3 grid(unsigned(per * 8));
   if (xdt == APR_F32 && ydt == APR_F32)
-    hipLaunchKernelGGL((conv1_kernel<K, float, float, INDEX>), grid, dim3(256), 0, s, args);
+    hipLaunchKernelGGL((conv1_kernel<K, float, float, INDEX>), grid, dim3(kConvThreads), 0, s, args);
   else if (xdt == APR_BF16 && ydt == APR_BF16)
-    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, __hip_bfloat16, INDEX>), grid, dim3(256), 0,
+    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, __hip_bfloat16, INDEX>), grid, dim3(kConvThreads), 0,
                        s, args);
   else if (xdt == APR_BF16 && ydt == APR_F32)
-    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, float, INDEX>), grid, dim3(256), 0, s, args);
+    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, float, INDEX>), grid, dim3(kConvThreads), 0, s, args);
   else
     APR_FAIL(APR_EUNSUPPORTED, "apr_conv: unsupported dtype combination");
   APR_HIP(hipGetLastError());
