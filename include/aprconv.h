@@ -51,6 +51,8 @@ typedef int32_t apr_status;
 /* apr_access_desc.flags */
 #define APR_VALIDATE_PARTITION 1u  /* check on the device that the cells partition the image */
 #define APR_VALIDATE_BALANCE 2u    /* check 26-neighbour 2:1 level balance */
+#define APR_BUILD_GATHER3 4u       /* also build the 3^3 gather map (multichannel, backward) */
+#define APR_BUILD_GATHER5 8u       /* also build the 5^3 gather map */
 
 #define APR_MAX_LEVELS 17          /* levels 0..16 (y_dim <= 65535) */
 
@@ -156,6 +158,9 @@ typedef struct {
   int32_t epilogue;      /* APR_EPI_* */
   float eps;             /* clamp of APR_EPI_RATIO */
   const void* epi_arg;   /* device [N_p], same dtype as y: u for RATIO and MUL */
+  const float* bias;     /* device FP32 [c_out] or NULL (gather path) */
+  int32_t relu;          /* nonzero: y = max(y, 0) after bias and residual (gather path) */
+  const void* residual;  /* device [N_p][c_out] of y's dtype added before relu, or NULL */
 } apr_conv_desc;
 
 /* y[p] = sum_o w_{l_p}[o] * V_{l_p}(c_p + o) for every particle p, with V_l
@@ -168,6 +173,32 @@ typedef struct {
  * [N_p][c_out], must not alias x or tree.  Asynchronous. */
 apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                     const float* w, void* y, void* stream);
+/* Paths: c_in = c_out = 1 without bias / relu / residual runs the LDS-patch
+ * kernels; every other request (multichannel Y[p,co] = b[co] + sum_{ci,o}
+ * W_l[co][ci][o] V_l[ci](c_p + o)) runs on the gather map and needs the handle
+ * built with APR_BUILD_GATHER3 / APR_BUILD_GATHER5 for d->k.  Supported
+ * (c_in, c_out): k = 3: (1,1) (1,16) (16,16) (16,1) (2,3); k = 5: (1,1) (2,3). */
+
+/* Gradient of apr_conv with respect to x (the transpose of the linear map
+ * x -> y, bias excluded): same-level taps, taps of level-(l+1) particles that
+ * read a level-l particle as their coarser source, and tree taps routed down
+ * through the child means (adjoint of Section 3.4's average).  dy: device FP32
+ * [N_p][c_out]; w: FP32 weights as in apr_conv; dx: device FP32 [N_p][c_in]
+ * (overwritten); dtree: device FP32 [N_t][c_in] scratch.  Needs the gather map
+ * for d->k.  Deterministic.  Asynchronous. */
+apr_status apr_conv_bwd_data(const apr_handle* h, const apr_conv_desc* d, const float* dy, const float* w,
+                             float* dx, float* dtree, void* stream);
+
+/* Workspace bytes of apr_conv_bwd_weight (FP64 block partials). */
+size_t apr_conv_bwd_weight_ws(const apr_handle* h, const apr_conv_desc* d);
+
+/* dw[l][co][ci][o] = sum over particles p of level l of dy[p][co] V_l[ci](c_p + o)
+ * (summed over levels when d->n_wlevels == 1).  x, tree: as in apr_conv
+ * (tree filled from x); dy: FP32 [N_p][c_out]; dw: FP32 (overwritten); ws:
+ * device workspace of apr_conv_bwd_weight_ws bytes.  FP32 block sums, FP64
+ * partials reduced in a fixed order: deterministic.  Asynchronous. */
+apr_status apr_conv_bwd_weight(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                               const float* dy, float* dw, void* ws, size_t ws_bytes, void* stream);
 
 /* Test support: for each listed particle and each tap (dz, dx, dy ascending)
  * write which element supplies V_l(c_p + o), computed by the convolution's own
@@ -177,6 +208,25 @@ apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, 
  * ascending and unique); out: device int64 [n][k^3].  Asynchronous. */
 apr_status apr_neighbor_map(const apr_handle* h, int32_t k, const int64_t* particles, int64_t n,
                             int64_t* out, void* stream);
+
+/* ----------------------------------------------------------------------
+ * Richardson-Lucy deconvolution on the APR (Section 6.2)
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace apr_richardson_lucy needs for this handle. */
+size_t apr_richardson_lucy_workspace(const apr_handle* h);
+
+/* n_iter iterations of  i <- i * corr(u / max(corr(i, w_flip_l), eps), w_l),
+ * i_0 = u, eps = eps_rel * max|u|: the Richardson-Lucy update with both
+ * convolutions replaced by APR convolutions and the PSF restricted to every
+ * level (Eq. restrict_stenc).  w and w_flip: device FP32 [n_wlevels][k^3], the
+ * per-level PSF and per-level flipped PSF (apr_stencil_levels with flip = 0
+ * and 1); u, out: device FP32 [N_p] (out may not alias u); work: device
+ * workspace of apr_richardson_lucy_workspace bytes.  Every tree is refilled
+ * from the array it belongs to.  Asynchronous. */
+apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_t n_wlevels, const float* w,
+                               const float* w_flip, const float* u, float* out, int32_t n_iter,
+                               float eps_rel, void* work, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* apr_last_error(void);

@@ -15,13 +15,15 @@ APR_OK, APR_EINVAL, APR_EUNBALANCED, APR_EPARTITION, APR_EUNSUPPORTED, APR_ENOME
 STATUS_NAMES = {0: "APR_OK", 1: "APR_EINVAL", 2: "APR_EUNBALANCED", 3: "APR_EPARTITION",
                 4: "APR_EUNSUPPORTED", 5: "APR_ENOMEM", 6: "APR_EDEVICE"}
 APR_F32, APR_BF16 = 0, 1
-APR_VALIDATE_PARTITION, APR_VALIDATE_BALANCE = 1, 2
+APR_VALIDATE_PARTITION, APR_VALIDATE_BALANCE, APR_BUILD_GATHER3, APR_BUILD_GATHER5 = 1, 2, 4, 8
 APR_MAX_LEVELS = 17
 APR_STENCIL_SAME, APR_STENCIL_RESTRICT, APR_STENCIL_ADAPTIVE = 0, 1, 2
 APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL = 0, 1, 2
 
 EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree", "apr_access_destroy",
-            "apr_fill_tree", "apr_stencil_levels", "apr_conv", "apr_neighbor_map", "apr_last_error"]
+            "apr_fill_tree", "apr_stencil_levels", "apr_conv", "apr_neighbor_map",
+            "apr_richardson_lucy_workspace", "apr_richardson_lucy", "apr_conv_bwd_data",
+            "apr_conv_bwd_weight_ws", "apr_conv_bwd_weight", "apr_last_error"]
 
 
 class AccessDesc(ctypes.Structure):
@@ -43,7 +45,7 @@ class AccessInfo(ctypes.Structure):
 class ConvDesc(ctypes.Structure):
     _fields_ = [("k", c_int32), ("c_in", c_int32), ("c_out", c_int32), ("n_wlevels", c_int32),
                 ("x_dtype", c_int32), ("y_dtype", c_int32), ("epilogue", c_int32), ("eps", c_float),
-                ("epi_arg", c_void_p)]
+                ("epi_arg", c_void_p), ("bias", c_void_p), ("relu", c_int32), ("residual", c_void_p)]
 
 
 class AprError(RuntimeError):
@@ -73,10 +75,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        c_void_p]
     lib.apr_conv.argtypes = [c_void_p, POINTER(ConvDesc), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.apr_neighbor_map.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_void_p]
+    lib.apr_richardson_lucy_workspace.argtypes = [c_void_p]
+    lib.apr_richardson_lucy_workspace.restype = ctypes.c_size_t
+    lib.apr_richardson_lucy.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_int32, c_float, c_void_p, c_void_p]
+    lib.apr_conv_bwd_data.argtypes = [c_void_p, POINTER(ConvDesc), c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]
+    lib.apr_conv_bwd_weight_ws.argtypes = [c_void_p, POINTER(ConvDesc)]
+    lib.apr_conv_bwd_weight_ws.restype = ctypes.c_size_t
+    lib.apr_conv_bwd_weight.argtypes = [c_void_p, POINTER(ConvDesc), c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, ctypes.c_size_t, c_void_p]
     lib.apr_last_error.argtypes = []
     lib.apr_last_error.restype = c_char_p
     for name in EXPORTED:
-        if name != "apr_last_error":
+        if name not in ("apr_last_error", "apr_richardson_lucy_workspace", "apr_conv_bwd_weight_ws"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

@@ -36,7 +36,7 @@ class AprAccess:
     """Device access structure of one APR (``apr_access_build``)."""
 
     def __init__(self, dims, l_min: int, l_max: int, y_idx: np.ndarray, xz_end: np.ndarray,
-                 validate: bool = True):
+                 validate: bool = True, gather=()):
         lib = L.load()
         self._lib = lib
         y = np.ascontiguousarray(y_idx, dtype=np.uint16)
@@ -49,6 +49,11 @@ class AprAccess:
         d.xz_end = e.ctypes.data if e.size else None
         d.n_rows = e.size
         d.flags = (L.APR_VALIDATE_PARTITION | L.APR_VALIDATE_BALANCE) if validate else 0
+        if 3 in gather:
+            d.flags |= L.APR_BUILD_GATHER3
+        if 5 in gather:
+            d.flags |= L.APR_BUILD_GATHER5
+        self.gather = tuple(gather)
         h = ctypes.c_void_p()
         L.check(lib.apr_access_build(ctypes.byref(d), _stream(), ctypes.byref(h)))
         self._h = h
@@ -69,8 +74,8 @@ class AprAccess:
                                for l in range(self.tree_l_min, self.tree_l_max + 1)}
 
     @classmethod
-    def from_input(cls, inp, validate: bool = True) -> "AprAccess":
-        return cls(inp.dims, inp.l_min, inp.l_max, inp.y_idx, inp.xz_end, validate=validate)
+    def from_input(cls, inp, validate: bool = True, gather=()) -> "AprAccess":
+        return cls(inp.dims, inp.l_min, inp.l_max, inp.y_idx, inp.xz_end, validate=validate, gather=gather)
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -132,31 +137,82 @@ def stencil_levels(w, mode: str, k: int, l_min: int, l_max: int, flip: bool = Fa
     return out.reshape((l_max - l_min + 1,) + lead + (k, k, k))
 
 
-def conv(acc: AprAccess, x: torch.Tensor, tree: torch.Tensor, w: torch.Tensor, k: int,
-         y: Optional[torch.Tensor] = None, out_dtype: Optional[torch.dtype] = None,
-         epilogue: Optional[str] = None, epi_arg: Optional[torch.Tensor] = None,
-         eps: float = 0.0) -> torch.Tensor:
-    """Single-channel APR convolution (``apr_conv``).  w: FP32 device tensor
-    [n_wlevels, k, k, k] with n_wlevels 1 or the number of levels."""
-    if w.dtype != torch.float32:
-        raise ValueError("weights are FP32")
-    nw = w.shape[0]
-    if nw not in (1, acc.n_levels) or w.numel() != nw * k ** 3:
-        raise ValueError("w must be [1 or n_levels, k, k, k]")
-    if x.shape[0] != acc.n_particles:
-        raise ValueError("x has the wrong number of particles")
-    if y is None:
-        y = torch.empty(acc.n_particles, dtype=out_dtype or x.dtype, device=x.device)
+def _desc(k, c_in, c_out, nw, x_dtype, y_dtype, epilogue=None, eps=0.0, epi_arg=None, bias=None,
+          relu=False, residual=None) -> L.ConvDesc:
     d = L.ConvDesc()
-    d.k, d.c_in, d.c_out, d.n_wlevels = k, 1, 1, nw
-    d.x_dtype, d.y_dtype = _DT[x.dtype], _DT[y.dtype]
+    d.k, d.c_in, d.c_out, d.n_wlevels = k, c_in, c_out, nw
+    d.x_dtype, d.y_dtype = _DT[x_dtype], _DT[y_dtype]
     d.epilogue = _EPI[epilogue]
     d.eps = float(eps)
     d.epi_arg = _ptr(epi_arg) if epi_arg is not None else None
+    d.bias = _ptr(bias) if bias is not None else None
+    d.relu = int(bool(relu))
+    d.residual = _ptr(residual) if residual is not None else None
+    return d
+
+
+def _wshape(acc: AprAccess, w: torch.Tensor, k: int):
+    """(n_wlevels, c_out, c_in) of FP32 weights [nw, k,k,k] or [nw, c_out, c_in, k,k,k]."""
+    if w.dtype != torch.float32:
+        raise ValueError("weights are FP32")
+    if w.dim() == 4:
+        nw, cout, cin = w.shape[0], 1, 1
+    elif w.dim() == 6:
+        nw, cout, cin = w.shape[0], w.shape[1], w.shape[2]
+    else:
+        raise ValueError("w must be [nw, k, k, k] or [nw, c_out, c_in, k, k, k]")
+    if nw not in (1, acc.n_levels) or w.shape[-1] != k or w.numel() != nw * cout * cin * k ** 3:
+        raise ValueError("w must hold 1 or n_levels stencils of side k")
+    return nw, cout, cin
+
+
+def conv(acc: AprAccess, x: torch.Tensor, tree: torch.Tensor, w: torch.Tensor, k: int,
+         y: Optional[torch.Tensor] = None, out_dtype: Optional[torch.dtype] = None,
+         epilogue: Optional[str] = None, epi_arg: Optional[torch.Tensor] = None,
+         eps: float = 0.0, bias: Optional[torch.Tensor] = None, relu: bool = False,
+         residual: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """APR convolution (``apr_conv``).  x [N_p] or [N_p, c_in]; w FP32
+    [nw, k,k,k] or [nw, c_out, c_in, k,k,k] with nw 1 or the number of levels."""
+    nw, cout, cin = _wshape(acc, w, k)
+    if x.shape[0] != acc.n_particles or (x.dim() == 2 and x.shape[1] != cin) or (x.dim() == 1 and cin != 1):
+        raise ValueError("x has the wrong shape")
+    if y is None:
+        shape = (acc.n_particles,) if (w.dim() == 4 and x.dim() == 1) else (acc.n_particles, cout)
+        y = torch.empty(shape, dtype=out_dtype or x.dtype, device=x.device)
+    d = _desc(k, cin, cout, nw, x.dtype, y.dtype, epilogue, eps, epi_arg, bias, relu, residual)
     L.check(acc._lib.apr_conv(acc.handle, ctypes.byref(d), _ptr(x),
                               _ptr(tree) if tree is not None and tree.numel() else None,
                               _ptr(w), _ptr(y), _stream()))
     return y
+
+
+def conv_bwd_data(acc: AprAccess, dy: torch.Tensor, w: torch.Tensor, k: int,
+                  dx: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Gradient of ``conv`` with respect to x (``apr_conv_bwd_data``); dy FP32."""
+    nw, cout, cin = _wshape(acc, w, k)
+    dy2 = dy.reshape(acc.n_particles, cout).contiguous()
+    if dx is None:
+        dx = torch.empty((acc.n_particles, cin), dtype=torch.float32, device=dy.device)
+    dt = torch.empty((max(acc.n_tree, 1), cin), dtype=torch.float32, device=dy.device)
+    d = _desc(k, cin, cout, nw, torch.float32, torch.float32)
+    L.check(acc._lib.apr_conv_bwd_data(acc.handle, ctypes.byref(d), _ptr(dy2), _ptr(w), _ptr(dx), _ptr(dt),
+                                       _stream()))
+    return dx
+
+
+def conv_bwd_weight(acc: AprAccess, x: torch.Tensor, tree: torch.Tensor, dy: torch.Tensor, k: int,
+                    nw: int, c_in: int, c_out: int) -> torch.Tensor:
+    """Gradient of ``conv`` with respect to the weights (``apr_conv_bwd_weight``):
+    FP32 [nw, c_out, c_in, k, k, k]."""
+    d = _desc(k, c_in, c_out, nw, x.dtype, torch.float32)
+    nbytes = int(acc._lib.apr_conv_bwd_weight_ws(acc.handle, ctypes.byref(d)))
+    ws = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=x.device)
+    dw = torch.empty((nw, c_out, c_in, k, k, k), dtype=torch.float32, device=x.device)
+    dy2 = dy.reshape(acc.n_particles, c_out).contiguous()
+    L.check(acc._lib.apr_conv_bwd_weight(acc.handle, ctypes.byref(d), _ptr(x),
+                                         _ptr(tree) if tree is not None and tree.numel() else None,
+                                         _ptr(dy2), _ptr(dw), _ptr(ws), nbytes, _stream()))
+    return dw
 
 
 def neighbor_map(acc: AprAccess, k: int, particles: torch.Tensor) -> torch.Tensor:
@@ -164,4 +220,21 @@ def neighbor_map(acc: AprAccess, k: int, particles: torch.Tensor) -> torch.Tenso
     p = particles.to(torch.int64).contiguous()
     out = torch.full((p.numel(), k ** 3), -2, dtype=torch.int64, device=p.device)
     L.check(acc._lib.apr_neighbor_map(acc.handle, k, _ptr(p), p.numel(), _ptr(out), _stream()))
+    return out
+
+
+def richardson_lucy(acc: AprAccess, u: torch.Tensor, psf, n_iter: int, eps_rel: float = 1e-12,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """APR Richardson-Lucy deconvolution of particle values u (FP32) with the
+    PSF restricted to every level (``apr_richardson_lucy``)."""
+    psf = np.asarray(psf, np.float64)
+    k = psf.shape[-1]
+    w = torch.from_numpy(stencil_levels(psf, "restrict", k, acc.l_min, acc.l_max)).to(u.device)
+    wf = torch.from_numpy(stencil_levels(psf, "restrict", k, acc.l_min, acc.l_max, flip=True)).to(u.device)
+    nbytes = int(acc._lib.apr_richardson_lucy_workspace(acc.handle))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=u.device)
+    if out is None:
+        out = torch.empty_like(u)
+    L.check(acc._lib.apr_richardson_lucy(acc.handle, k, w.shape[0], _ptr(w), _ptr(wf), _ptr(u), _ptr(out),
+                                         int(n_iter), float(eps_rel), _ptr(ws), _stream()))
     return out

@@ -312,6 +312,8 @@ __global__ void tile_compact_kernel(TileLevels tl, const uint32_t* __restrict__ 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+apr_status build_gather_map(const apr_handle* h, int k, int32_t* map32, hipStream_t s);
+
 static int finest_level(const int32_t* dims) {
   int32_t mx = std::max(dims[0], std::max(dims[1], dims[2]));
   int l = 0;
@@ -578,6 +580,19 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
     hipLaunchKernelGGL(tile_compact_kernel, dim3(unsigned((ntot + 255) / 256)), dim3(256), 0, s,
                        tl, sc, raw, h->tiles, ntot);
     APR_TRY_HIP(hipGetLastError());
+  }
+  // ---- gather maps (multichannel convolution and the backward passes)
+  for (int gi = 0; gi < 2; ++gi) {
+    const int k = gi == 0 ? 3 : 5;
+    if (!(d->flags & (gi == 0 ? APR_BUILD_GATHER3 : APR_BUILD_GATHER5))) continue;
+    if (h->n_p >= (int64_t(1) << 30) - 1 || h->n_t >= (int64_t(1) << 30) - 1) {
+      set_error("apr_access_build: gather maps need fewer than 2^30 particles and tree nodes");
+      free_handle(h);
+      for (void* p : tmp) (void)hipFree(p);
+      return APR_EUNSUPPORTED;
+    }
+    APR_TRY(dev_alloc(h, &h->gmap[gi], h->n_p * int64_t(k * k * k)));
+    APR_TRY(build_gather_map(h, k, h->gmap[gi], s));
   }
   APR_TRY_HIP(hipStreamSynchronize(s));
   for (void* p : tmp) (void)hipFree(p);

@@ -111,6 +111,7 @@ struct apr_handle {
   uint32_t* tend = nullptr;   // tree row ends [n_trows]
   uint64_t* tiles = nullptr;  // conv tiles [n_tiles], finest level first
   int64_t n_tiles = 0;
+  int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
 };

@@ -47,10 +47,13 @@ struct ConvArgs {
   void* y;
   int32_t epi;
   float eps;
+  const float* eps_dev;   // when set, the ratio clamp is read from device memory
   const void* epi_arg;
   const int64_t* sel;   // neighbour-map mode: sorted particle list
   int64_t n_sel;
   int64_t* map;         // neighbour-map mode output [n_sel][k^3]
+  int32_t* map32;       // gather-map mode: every particle, [k^3][N_p] (type << 30 | index, -1 pad;
+                        // n_sel holds N_p)
 };
 
 // exclusive scan of n LDS entries in place by one wave (E entries per lane,
@@ -408,6 +411,18 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
       const uint32_t idx = opd[c] + (jt - ocap[c]);
       const int hz = c / TX_, hx = c % TX_;   // halo row of the tap (-R, -R) is (hz, hx)
       if constexpr (INDEX) {
+        if (a.map32) {
+          // tap-major layout [k^3][N_p]: consecutive particles are adjacent
+          int q = 0;
+          for (int dz = 0; dz < K; ++dz)
+            for (int dx = 0; dx < K; ++dx)
+              for (int dy = 0; dy < K; ++dy) {
+                const int64_t code = int64_t(patch[((hz + dz) * HX + hx + dx) * PY + p0 - R + dy]);
+                a.map32[size_t(q++) * size_t(a.n_sel) + idx] =
+                    code < 0 ? -1 : int32_t(((code >> 40) << 30) | (code & ((int64_t(1) << 30) - 1)));
+              }
+          continue;
+        }
         int64_t lo = 0, hi = a.n_sel;
         while (lo < hi) {
           const int64_t mid = (lo + hi) >> 1;
@@ -436,7 +451,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
         TY* yo = static_cast<TY*>(a.y);
         if (a.epi == APR_EPI_RATIO) {
           const float u = to_f32<TY>(static_cast<const TY*>(a.epi_arg)[idx]);
-          acc = u / fmaxf(acc, a.eps);
+          acc = u / fmaxf(acc, a.eps_dev ? *a.eps_dev : a.eps);
         } else if (a.epi == APR_EPI_MUL) {
           acc *= to_f32<TY>(static_cast<const TY*>(a.epi_arg)[idx]);
         }
@@ -482,12 +497,24 @@ static ConvArgs base_args(const apr_handle* h) {
 
 using namespace apr;
 
+namespace apr {
+apr_status conv_impl(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                     const float* w, void* y, const float* eps_dev, void* stream);
+apr_status mc_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                   const float* w, void* y, hipStream_t s);
+}
+
 extern "C" apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x,
                                const void* tree, const float* w, void* y, void* stream) {
+  return apr::conv_impl(h, d, x, tree, w, y, nullptr, stream);
+}
+
+apr_status apr::conv_impl(const apr_handle* h, const apr_conv_desc* d, const void* x,
+                          const void* tree, const float* w, void* y, const float* eps_dev,
+                          void* stream) {
   if (!h || !d) APR_FAIL(APR_EINVAL, "apr_conv: null handle or descriptor");
   if (d->k != 3 && d->k != 5) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: k must be 3 or 5");
-  if (d->c_in != 1 || d->c_out != 1)
-    APR_FAIL(APR_EUNSUPPORTED, "apr_conv: this build supports c_in = c_out = 1");
+  if (d->c_in < 1 || d->c_out < 1) APR_FAIL(APR_EINVAL, "apr_conv: channel counts must be >= 1");
   const int nl = h->meta.l_max - h->meta.l_min + 1;
   if (d->n_wlevels != 1 && d->n_wlevels != nl)
     APR_FAIL(APR_EINVAL, "apr_conv: n_wlevels must be 1 or l_max - l_min + 1");
@@ -497,6 +524,10 @@ extern "C" apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, cons
   if (!x || !w || !y || (h->n_t && !tree)) APR_FAIL(APR_EINVAL, "apr_conv: null buffer");
   if (d->epilogue != APR_EPI_NONE && !d->epi_arg) APR_FAIL(APR_EINVAL, "apr_conv: null epi_arg");
   if (y == x || y == tree) APR_FAIL(APR_EINVAL, "apr_conv: y must not alias x or tree");
+  if (d->c_in != 1 || d->c_out != 1 || d->bias || d->relu || d->residual) {
+    if (d->epilogue != APR_EPI_NONE) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: epilogues need c_in = c_out = 1");
+    return mc_conv(h, d, x, tree, w, y, static_cast<hipStream_t>(stream));
+  }
   ConvArgs a = base_args(h);
   a.x = x;
   a.tree = tree;
@@ -505,6 +536,7 @@ extern "C" apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, cons
   a.y = y;
   a.epi = d->epilogue;
   a.eps = d->eps;
+  a.eps_dev = eps_dev;
   a.epi_arg = d->epi_arg;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return d->k == 3 ? launch_conv<3, false>(a, d->x_dtype, d->y_dtype, s)
@@ -525,3 +557,16 @@ extern "C" apr_status apr_neighbor_map(const apr_handle* h, int32_t k, const int
   return k == 3 ? launch_conv<3, true>(a, APR_F32, APR_F32, s)
                 : launch_conv<5, true>(a, APR_F32, APR_F32, s);
 }
+
+namespace apr {
+// gather map of every particle for stencil side k, written by the
+// convolution's own patch builder (int32 code: type << 30 | index, -1 pad;
+// type 1 = APR level l, 2 = APR level l-1, 3 = tree level l)
+apr_status build_gather_map(const apr_handle* h, int k, int32_t* map32, hipStream_t s) {
+  if (h->n_tiles == 0) return APR_OK;
+  ConvArgs a = base_args(h);
+  a.map32 = map32;
+  a.n_sel = h->n_p;
+  return k == 3 ? launch_conv<3, true>(a, APR_F32, APR_F32, s) : launch_conv<5, true>(a, APR_F32, APR_F32, s);
+}
+}  // namespace apr

@@ -1,0 +1,531 @@
+// Multichannel APR convolution and the adjoint of APR convolution, built on
+// the per-APR gather map (for every particle and tap: which element supplies
+// V_l(c_p + o) -- written once by the convolution's own patch builder).
+//
+//   forward      Y[p, co] = b[co] + sum_o sum_ci W_l[co, ci, o] Xcat[src(p, o), ci]
+//   data grad    the transpose of the forward, evaluated as gathers:
+//                  * same-level readers of a particle s: the particle at
+//                    c_s - o reads s with tap o  (s's own gather map, flipped);
+//                  * finer readers: level-(l+1) particles whose taps land in
+//                    one of the eight children of s (row lookups);
+//                  * tree readers: level-L particles whose taps land on a tree
+//                    node t (row lookups), then the adjoint of the child mean
+//                    pushed from the coarsest tree level down to the particles.
+//   weight grad  dW_l[co, ci, o] = sum_{p at level l} dY[p, co] Xcat[src(p, o), ci],
+//                per-block FP32 sums, FP64 partials, fixed-order FP64 reduce.
+// Every output has a single writer and a fixed summation order: results are
+// deterministic.
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace apr {
+
+constexpr int kGWaves = 4;   // waves per block in the row-based kernels
+constexpr uint32_t kIdxMask = (1u << 30) - 1;
+constexpr uint32_t kPad = 0xffffffffu;   // gather-map entry of a tap outside the image
+
+using cfloat = const __attribute__((address_space(4))) float;
+__device__ inline cfloat* as_const(const float* p) { return (cfloat*)(uintptr_t)p; }
+
+// first index in [b, e) with ys[i] >= y (rows are sorted)
+__device__ inline uint32_t lower_bound_y(const uint16_t* ys, uint32_t b, uint32_t e, int y) {
+  while (b < e) {
+    const uint32_t mid = (b + e) >> 1;
+    if (int(ys[mid]) < y) b = mid + 1; else e = mid;
+  }
+  return b;
+}
+
+template <typename T>
+__device__ inline void load_row(const T* base, int C, float* v) {
+  for (int c = 0; c < C; ++c) v[c] = to_f32<T>(base[c]);
+}
+
+// ---------------------------------------------------------------------------
+// Multichannel forward: one wave per particle row of level l, one lane per
+// particle.  Weights of level l are uniform (scalar loads).
+// ---------------------------------------------------------------------------
+template <int K, int CIN, int COUT, typename TX, typename TY>
+__global__ __launch_bounds__(64 * kGWaves) void mc_fwd_kernel(
+    Meta m, int l, const uint32_t* __restrict__ pend, const int32_t* __restrict__ gmap, int64_t n_p,
+    const TX* __restrict__ x, const TX* __restrict__ tree, const float* w_level,
+    const float* bias, int relu, const TY* __restrict__ residual, TY* __restrict__ y) {
+  constexpr int K3 = K * K * K;
+  const int64_t row = int64_t(blockIdx.x) * kGWaves + threadIdx.x / 64;
+  if (row >= int64_t(m.dz[l]) * m.dx[l]) return;
+  uint32_t b, e;
+  row_range(pend, m.prow[l] + uint32_t(row), b, e);
+  cfloat* W = as_const(w_level);
+  cfloat* B = bias ? as_const(bias) : nullptr;
+  for (uint32_t p = b + lane_id(); p < e; p += 64) {
+    float acc[COUT];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] = B ? B[co] : 0.f;
+#pragma unroll 1
+    for (int q = 0; q < K3; ++q) {
+      const uint32_t g = gmap[size_t(q) * size_t(n_p) + p];
+      if (g == kPad) continue;
+      const uint32_t idx = g & kIdxMask;
+      const TX* src = ((g >> 30) == 3) ? tree + size_t(idx) * CIN : x + size_t(idx) * CIN;
+      float v[CIN];
+      load_row<TX>(src, CIN, v);
+#pragma unroll
+      for (int co = 0; co < COUT; ++co)
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci) acc[co] = fmaf(W[(co * CIN + ci) * K3 + q], v[ci], acc[co]);
+    }
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) {
+      float o = acc[co];
+      if (residual) o += to_f32<TY>(residual[size_t(p) * COUT + co]);
+      if (relu) o = fmaxf(o, 0.f);
+      y[size_t(p) * COUT + co] = from_f32<TY>(o);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Data gradient, part 1: for every particle s of level l, the taps of
+// same-level particles (flipped own gather map) and of level-(l+1) particles
+// landing in its children (row lookups).  Writes dx[s] (overwrites).
+// ---------------------------------------------------------------------------
+template <int K, int CIN, int COUT>
+__global__ __launch_bounds__(64 * kGWaves) void bwd_particle_kernel(
+    Meta m, int l, const uint16_t* __restrict__ py, const uint32_t* __restrict__ pend,
+    const int32_t* __restrict__ gmap, int64_t n_p, const float* __restrict__ dy, const float* w_l,
+    const float* w_fine, float* __restrict__ dx) {
+  constexpr int R = K / 2, K3 = K * K * K;
+  const int64_t row = int64_t(blockIdx.x) * kGWaves + threadIdx.x / 64;
+  if (row >= int64_t(m.dz[l]) * m.dx[l]) return;
+  const int z = int(row / m.dx[l]), xr = int(row % m.dx[l]);
+  uint32_t b, e;
+  row_range(pend, m.prow[l] + uint32_t(row), b, e);
+  cfloat* W = as_const(w_l);
+  cfloat* WF = w_fine ? as_const(w_fine) : nullptr;
+  const int lf = l + 1;
+  for (uint32_t s = b + lane_id(); s < e; s += 64) {
+    float acc[CIN];
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
+    // same level: the element at c_s - o is entry (k^3 - 1 - q) of s's map
+#pragma unroll 1
+    for (int q = 0; q < K3; ++q) {
+      const uint32_t g = gmap[size_t(K3 - 1 - q) * size_t(n_p) + s];
+      if (g == kPad || (g >> 30) != 1) continue;
+      const float* gp = dy + size_t(g & kIdxMask) * COUT;
+      float gv[COUT];
+#pragma unroll
+      for (int co = 0; co < COUT; ++co) gv[co] = gp[co];
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) acc[ci] = fmaf(W[(co * CIN + ci) * K3 + q], gv[co], acc[ci]);
+    }
+    // finer level: particles p at 2 c_s + d, d in [-R, 1+R]^3, whose tap
+    // o = b - d lands on child 2 c_s + b (b in {0,1}^3, child in the image)
+    if (WF) {
+      const int ys = py[s];
+      for (int dz = -R; dz <= 1 + R; ++dz)
+        for (int dxo = -R; dxo <= 1 + R; ++dxo) {
+          const int zz = 2 * z + dz, xx = 2 * xr + dxo;
+          if (zz < 0 || xx < 0 || zz >= m.dz[lf] || xx >= m.dx[lf]) continue;
+          uint32_t rb, re;
+          row_range(pend, m.prow[lf] + uint32_t(zz) * m.dx[lf] + xx, rb, re);
+          for (uint32_t i = lower_bound_y(py, rb, re, 2 * ys - R); i < re; ++i) {
+            const int dyo = int(py[i]) - 2 * ys;
+            if (dyo > 1 + R) break;
+            float gv[COUT];
+#pragma unroll
+            for (int co = 0; co < COUT; ++co) gv[co] = dy[size_t(i) * COUT + co];
+            for (int bz = 0; bz < 2; ++bz)
+              for (int bx = 0; bx < 2; ++bx)
+                for (int by = 0; by < 2; ++by) {
+                  if (2 * z + bz >= m.dz[lf] || 2 * xr + bx >= m.dx[lf] || 2 * ys + by >= m.dy[lf]) continue;
+                  const int oz = bz - dz, ox = bx - dxo, oy = by - dyo;
+                  if (oz < -R || oz > R || ox < -R || ox > R || oy < -R || oy > R) continue;
+                  const int q = ((oz + R) * K + (ox + R)) * K + (oy + R);
+#pragma unroll
+                  for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+                    for (int co = 0; co < COUT; ++co)
+                      acc[ci] = fmaf(WF[(co * CIN + ci) * K3 + q], gv[co], acc[ci]);
+                }
+          }
+        }
+    }
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) dx[size_t(s) * CIN + ci] = acc[ci];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Data gradient, part 2: tree node t of level L receives the taps of level-L
+// particles landing on it (row lookups).  Writes dt[t] (overwrites; zero for
+// levels without particles).
+// ---------------------------------------------------------------------------
+template <int K, int CIN, int COUT>
+__global__ __launch_bounds__(64 * kGWaves) void bwd_tree_kernel(
+    Meta m, int L, const uint16_t* __restrict__ py, const uint32_t* __restrict__ pend,
+    const uint16_t* __restrict__ ty, const uint32_t* __restrict__ tend, const float* __restrict__ dy,
+    const float* w_L, float* __restrict__ dt) {
+  constexpr int R = K / 2, K3 = K * K * K;
+  const int64_t row = int64_t(blockIdx.x) * kGWaves + threadIdx.x / 64;
+  if (row >= int64_t(m.dz[L]) * m.dx[L]) return;
+  const int z = int(row / m.dx[L]), xr = int(row % m.dx[L]);
+  uint32_t b, e;
+  row_range(tend, m.trow[L] + uint32_t(row), b, e);
+  const bool has_p = L >= m.l_min && L <= m.l_max && w_L;
+  cfloat* W = has_p ? as_const(w_L) : nullptr;
+  for (uint32_t t = b + lane_id(); t < e; t += 64) {
+    float acc[CIN];
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
+    if (has_p) {
+      const int yt = ty[t];
+      for (int oz = -R; oz <= R; ++oz)
+        for (int ox = -R; ox <= R; ++ox) {
+          const int zz = z - oz, xx = xr - ox;   // reader p at c_t - o
+          if (zz < 0 || xx < 0 || zz >= m.dz[L] || xx >= m.dx[L]) continue;
+          uint32_t rb, re;
+          row_range(pend, m.prow[L] + uint32_t(zz) * m.dx[L] + xx, rb, re);
+          for (uint32_t i = lower_bound_y(py, rb, re, yt - R); i < re; ++i) {
+            const int oy = yt - int(py[i]);
+            if (oy < -R) break;
+            const int q = ((oz + R) * K + (ox + R)) * K + (oy + R);
+#pragma unroll
+            for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+              for (int co = 0; co < COUT; ++co)
+                acc[ci] = fmaf(W[(co * CIN + ci) * K3 + q], dy[size_t(i) * COUT + co], acc[ci]);
+          }
+        }
+    }
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) dt[size_t(t) * CIN + ci] = acc[ci];
+  }
+}
+
+// number of children of a level-L cell that lie in the image
+__device__ inline int n_children(const Meta& m, int L, int z, int x, int y) {
+  const int C = L + 1;
+  return (2 * z + 1 < m.dz[C] ? 2 : 1) * (2 * x + 1 < m.dx[C] ? 2 : 1) * (2 * y + 1 < m.dy[C] ? 2 : 1);
+}
+
+// ---------------------------------------------------------------------------
+// Data gradient, part 3: adjoint of the child mean.  For every element at
+// level L (tree node, or particle when `to_particles`), add its parent's
+// accumulated gradient divided by the parent's child count.  Launched level
+// by level from the coarsest, so the parent's value is final.
+// ---------------------------------------------------------------------------
+template <int CIN>
+__global__ __launch_bounds__(64 * kGWaves) void push_down_kernel(
+    Meta m, int L, const uint16_t* __restrict__ ys, const uint32_t* __restrict__ ends, uint32_t row0,
+    const uint16_t* __restrict__ ty, const uint32_t* __restrict__ tend, const float* __restrict__ dt,
+    float* __restrict__ out) {
+  const int64_t row = int64_t(blockIdx.x) * kGWaves + threadIdx.x / 64;
+  if (row >= int64_t(m.dz[L]) * m.dx[L]) return;
+  const int z = int(row / m.dx[L]), xr = int(row % m.dx[L]);
+  uint32_t b, e;
+  row_range(ends, row0 + uint32_t(row), b, e);
+  if (b == e) return;
+  const int P = L - 1;
+  uint32_t pb, pe;
+  row_range(tend, m.trow[P] + uint32_t(z >> 1) * m.dx[P] + (xr >> 1), pb, pe);
+  for (uint32_t i = b + lane_id(); i < e; i += 64) {
+    const int yv = ys[i];
+    const uint32_t par = lower_bound_y(ty, pb, pe, yv >> 1);   // the parent exists by construction
+    const float inv = 1.f / float(n_children(m, P, z >> 1, xr >> 1, yv >> 1));
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) out[size_t(i) * CIN + ci] += dt[size_t(par) * CIN + ci] * inv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: block j of level l sums dY[p, co] * Xcat[src(p, o), ci]
+// over its particles (staged PCH at a time in LDS) for every (co, ci, o), in
+// FP32, and writes an FP64 partial.
+// ---------------------------------------------------------------------------
+constexpr int kWgtThreads = 256;
+constexpr int kWgtParticles = 2048;   // particles per block
+
+template <int K, int CIN, int COUT, typename TX>
+__global__ __launch_bounds__(kWgtThreads) void bwd_weight_partial_kernel(
+    int64_t p_begin, int64_t p_end, const int32_t* __restrict__ gmap, int64_t n_p,
+    const TX* __restrict__ x, const TX* __restrict__ tree, const float* __restrict__ dy,
+    double* __restrict__ partial) {
+  constexpr int K3 = K * K * K;
+  constexpr int NOUT = COUT * CIN * K3;
+  constexpr int PCH = (K3 * CIN >= 2000) ? 8 : ((K3 * CIN >= 500) ? 16 : 32);
+  constexpr int NPT = (NOUT + kWgtThreads - 1) / kWgtThreads;   // outputs per thread
+  __shared__ float sv[PCH][K3 * CIN];
+  __shared__ float sg[PCH][COUT];
+  const int tid = threadIdx.x;
+  const int64_t blk_b = p_begin + int64_t(blockIdx.x) * kWgtParticles;
+  const int64_t blk_e = min(p_end, blk_b + kWgtParticles);
+  float acc[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) acc[j] = 0.f;
+  for (int64_t c0 = blk_b; c0 < blk_e; c0 += PCH) {
+    const int np = int(min<int64_t>(PCH, blk_e - c0));
+    __syncthreads();
+    for (int j = tid; j < PCH * K3; j += kWgtThreads) {
+      const int pp = j / K3, q = j % K3;
+      float v[CIN];
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci) v[ci] = 0.f;
+      if (pp < np) {
+        const uint32_t g = gmap[size_t(q) * size_t(n_p) + size_t(c0 + pp)];
+        if (g != kPad) {
+          const uint32_t idx = g & kIdxMask;
+          load_row<TX>(((g >> 30) == 3) ? tree + size_t(idx) * CIN : x + size_t(idx) * CIN, CIN, v);
+        }
+      }
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci) sv[pp][q * CIN + ci] = v[ci];
+    }
+    for (int j = tid; j < PCH * COUT; j += kWgtThreads) {
+      const int pp = j / COUT, co = j % COUT;
+      sg[pp][co] = (pp < np) ? dy[size_t(c0 + pp) * COUT + co] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < NPT; ++jj) {
+      const int o = tid + jj * kWgtThreads;   // o = (co * CIN + ci) * K3 + q
+      if (o >= NOUT) break;
+      const int q = o % K3, ci = (o / K3) % CIN, co = o / (K3 * CIN);
+      float s = acc[jj];
+      for (int pp = 0; pp < np; ++pp) s = fmaf(sg[pp][co], sv[pp][q * CIN + ci], s);
+      acc[jj] = s;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < NPT; ++jj) {
+    const int o = tid + jj * kWgtThreads;
+    if (o < NOUT) partial[size_t(blockIdx.x) * NOUT + o] = double(acc[jj]);
+  }
+}
+
+// dw[lo][o] = sum over the blocks [blk_b, blk_e) of partial[blk][o], in order
+__global__ void bwd_weight_reduce_kernel(const double* __restrict__ partial, int64_t blk_b, int64_t blk_e,
+                                         int nout, float* __restrict__ dw) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int64_t j = blk_b; j < blk_e; ++j) s += partial[size_t(j) * nout + o];
+  dw[o] = float(s);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static int level_blocks(const apr_handle* h, int l) {
+  return int((h->per_level_p[l] + kWgtParticles - 1) / kWgtParticles);
+}
+
+static int64_t level_first(const apr_handle* h, int l) {
+  int64_t b = 0;
+  for (int q = h->meta.l_min; q < l; ++q) b += h->per_level_p[q];
+  return b;
+}
+
+static const int32_t* gather_map(const apr_handle* h, int k) { return h->gmap[k == 3 ? 0 : 1]; }
+
+#define APR_CH_DISPATCH(CIN_, COUT_, ...)                                            \
+  if (cin == CIN_ && cout == COUT_) {                                                \
+    constexpr int CI = CIN_, CO = COUT_;                                             \
+    __VA_ARGS__;                                                                     \
+  }
+
+template <int K, int CI, int CO, typename TX, typename TY>
+static void launch_mc_fwd(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                          const float* w, void* y, hipStream_t s) {
+  const Meta& m = h->meta;
+  for (int l = m.l_min; l <= m.l_max; ++l) {
+    if (!h->per_level_p[l]) continue;
+    const int64_t rows = int64_t(m.dz[l]) * m.dx[l];
+    const float* wl = w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * CO * CI * K * K * K;
+    hipLaunchKernelGGL((mc_fwd_kernel<K, CI, CO, TX, TY>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
+                       dim3(64 * kGWaves), 0, s, m, l, h->pend, gather_map(h, K), h->n_p,
+                       static_cast<const TX*>(x), static_cast<const TX*>(tree), wl, d->bias, d->relu,
+                       static_cast<const TY*>(d->residual), static_cast<TY*>(y));
+  }
+}
+
+template <int K, int CI, int CO>
+static apr_status mc_fwd_dtypes(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                                const float* w, void* y, hipStream_t s) {
+  if (d->x_dtype == APR_F32 && d->y_dtype == APR_F32)
+    launch_mc_fwd<K, CI, CO, float, float>(h, d, x, tree, w, y, s);
+  else if (d->x_dtype == APR_BF16 && d->y_dtype == APR_BF16)
+    launch_mc_fwd<K, CI, CO, __hip_bfloat16, __hip_bfloat16>(h, d, x, tree, w, y, s);
+  else if (d->x_dtype == APR_BF16 && d->y_dtype == APR_F32)
+    launch_mc_fwd<K, CI, CO, __hip_bfloat16, float>(h, d, x, tree, w, y, s);
+  else if (d->x_dtype == APR_F32 && d->y_dtype == APR_BF16)
+    launch_mc_fwd<K, CI, CO, float, __hip_bfloat16>(h, d, x, tree, w, y, s);
+  else
+    APR_FAIL(APR_EUNSUPPORTED, "apr_conv: unsupported dtype combination");
+  APR_HIP(hipGetLastError());
+  return APR_OK;
+}
+
+apr_status mc_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                   const float* w, void* y, hipStream_t s) {
+  if (!gather_map(h, d->k))
+    APR_FAIL(APR_EINVAL, "apr_conv: this path needs the gather map; build the access with "
+                         "APR_BUILD_GATHER3 / APR_BUILD_GATHER5");
+  const int cin = d->c_in, cout = d->c_out;
+  if (d->k == 3) {
+    APR_CH_DISPATCH(1, 1, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
+    APR_CH_DISPATCH(1, 16, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
+    APR_CH_DISPATCH(16, 16, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
+    APR_CH_DISPATCH(16, 1, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
+    APR_CH_DISPATCH(2, 3, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
+  } else {
+    APR_CH_DISPATCH(1, 1, return mc_fwd_dtypes<5, CI, CO>(h, d, x, tree, w, y, s))
+    APR_CH_DISPATCH(2, 3, return mc_fwd_dtypes<5, CI, CO>(h, d, x, tree, w, y, s))
+  }
+  APR_FAIL(APR_EUNSUPPORTED, "apr_conv: unsupported (k, c_in, c_out); supported: k=3 (1,1) (1,16) "
+                             "(16,16) (16,1) (2,3); k=5 (1,1) (2,3)");
+}
+
+template <int K, int CI, int CO>
+static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, const float* dy, const float* w,
+                                float* dx, float* dt, hipStream_t s) {
+  const Meta& m = h->meta;
+  constexpr int K3 = K * K * K;
+  auto wlev = [&](int l) { return w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * CO * CI * K3; };
+  for (int l = m.l_min; l <= m.l_max; ++l) {
+    const int64_t rows = int64_t(m.dz[l]) * m.dx[l];
+    const float* wf = (l + 1 <= m.l_max && h->per_level_p[l + 1]) ? wlev(l + 1) : nullptr;
+    hipLaunchKernelGGL((bwd_particle_kernel<K, CI, CO>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
+                       dim3(64 * kGWaves), 0, s, m, l, h->py, h->pend, gather_map(h, K), h->n_p, dy, wlev(l),
+                       wf, dx);
+  }
+  for (int L = m.t_lo; L <= m.t_hi; ++L) {
+    const int64_t rows = int64_t(m.dz[L]) * m.dx[L];
+    const float* wL = (L >= m.l_min) ? wlev(L) : nullptr;
+    hipLaunchKernelGGL((bwd_tree_kernel<K, CI, CO>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
+                       dim3(64 * kGWaves), 0, s, m, L, h->py, h->pend, h->ty, h->tend, dy, wL, dt);
+  }
+  // adjoint of the child means, coarsest tree level first
+  for (int L = m.t_lo + 1; L <= m.t_hi; ++L) {
+    const int64_t rows = int64_t(m.dz[L]) * m.dx[L];
+    hipLaunchKernelGGL((push_down_kernel<CI>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
+                       dim3(64 * kGWaves), 0, s, m, L, h->ty, h->tend, m.trow[L], h->ty, h->tend, dt, dt);
+  }
+  for (int l = std::max(m.l_min, m.t_lo + 1); l <= m.l_max; ++l) {
+    if (!h->per_level_p[l]) continue;
+    const int64_t rows = int64_t(m.dz[l]) * m.dx[l];
+    hipLaunchKernelGGL((push_down_kernel<CI>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
+                       dim3(64 * kGWaves), 0, s, m, l, h->py, h->pend, m.prow[l], h->ty, h->tend, dt, dx);
+  }
+  APR_HIP(hipGetLastError());
+  return APR_OK;
+}
+
+template <int K, int CI, int CO, typename TX>
+static apr_status bwd_weight_impl(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                                  const float* dy, float* dw, double* ws, hipStream_t s) {
+  const Meta& m = h->meta;
+  constexpr int NOUT = CO * CI * K * K * K;
+  int64_t blk = 0;
+  for (int l = m.l_min; l <= m.l_max; ++l) {
+    const int nb = level_blocks(h, l);
+    if (!nb) continue;
+    const int64_t b = level_first(h, l);
+    hipLaunchKernelGGL((bwd_weight_partial_kernel<K, CI, CO, TX>), dim3(nb), dim3(kWgtThreads), 0, s, b,
+                       b + h->per_level_p[l], gather_map(h, K), h->n_p, static_cast<const TX*>(x),
+                       static_cast<const TX*>(tree), dy, ws + size_t(blk) * NOUT);
+    blk += nb;
+  }
+  const unsigned rg = unsigned((NOUT + 255) / 256);
+  if (d->n_wlevels == 1) {
+    hipLaunchKernelGGL(bwd_weight_reduce_kernel, dim3(rg), dim3(256), 0, s, ws, int64_t(0), blk, NOUT, dw);
+  } else {
+    int64_t bb = 0;
+    for (int l = m.l_min; l <= m.l_max; ++l) {
+      const int nb = level_blocks(h, l);
+      hipLaunchKernelGGL(bwd_weight_reduce_kernel, dim3(rg), dim3(256), 0, s, ws, bb, bb + nb, NOUT,
+                         dw + size_t(l - m.l_min) * NOUT);
+      bb += nb;
+    }
+  }
+  APR_HIP(hipGetLastError());
+  return APR_OK;
+}
+
+static apr_status check_desc(const apr_handle* h, const apr_conv_desc* d, const char* who) {
+  if (!h || !d) APR_FAIL(APR_EINVAL, std::string(who) + ": null handle or descriptor");
+  if (d->k != 3 && d->k != 5) APR_FAIL(APR_EUNSUPPORTED, std::string(who) + ": k must be 3 or 5");
+  const int nl = h->meta.l_max - h->meta.l_min + 1;
+  if (d->n_wlevels != 1 && d->n_wlevels != nl)
+    APR_FAIL(APR_EINVAL, std::string(who) + ": n_wlevels must be 1 or l_max - l_min + 1");
+  if (!gather_map(h, d->k))
+    APR_FAIL(APR_EINVAL, std::string(who) + ": build the access with APR_BUILD_GATHER3 / APR_BUILD_GATHER5");
+  return APR_OK;
+}
+
+}  // namespace apr
+
+using namespace apr;
+
+extern "C" apr_status apr_conv_bwd_data(const apr_handle* h, const apr_conv_desc* d, const float* dy,
+                                        const float* w, float* dx, float* dtree, void* stream) {
+  apr_status st = check_desc(h, d, "apr_conv_bwd_data");
+  if (st != APR_OK) return st;
+  if (h->n_p == 0) return APR_OK;
+  if (!dy || !w || !dx || (h->n_t && !dtree)) APR_FAIL(APR_EINVAL, "apr_conv_bwd_data: null buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int cin = d->c_in, cout = d->c_out;
+  if (d->k == 3) {
+    APR_CH_DISPATCH(1, 1, return bwd_data_impl<3, CI, CO>(h, d, dy, w, dx, dtree, s))
+    APR_CH_DISPATCH(1, 16, return bwd_data_impl<3, CI, CO>(h, d, dy, w, dx, dtree, s))
+    APR_CH_DISPATCH(16, 16, return bwd_data_impl<3, CI, CO>(h, d, dy, w, dx, dtree, s))
+    APR_CH_DISPATCH(16, 1, return bwd_data_impl<3, CI, CO>(h, d, dy, w, dx, dtree, s))
+    APR_CH_DISPATCH(2, 3, return bwd_data_impl<3, CI, CO>(h, d, dy, w, dx, dtree, s))
+  } else {
+    APR_CH_DISPATCH(1, 1, return bwd_data_impl<5, CI, CO>(h, d, dy, w, dx, dtree, s))
+    APR_CH_DISPATCH(2, 3, return bwd_data_impl<5, CI, CO>(h, d, dy, w, dx, dtree, s))
+  }
+  APR_FAIL(APR_EUNSUPPORTED, "apr_conv_bwd_data: unsupported (k, c_in, c_out)");
+}
+
+extern "C" size_t apr_conv_bwd_weight_ws(const apr_handle* h, const apr_conv_desc* d) {
+  if (!h || !d || (d->k != 3 && d->k != 5) || d->c_in < 1 || d->c_out < 1) return 0;
+  int64_t nb = 0;
+  for (int l = h->meta.l_min; l <= h->meta.l_max; ++l) nb += level_blocks(h, l);
+  return size_t(nb) * size_t(d->c_in) * size_t(d->c_out) * size_t(d->k * d->k * d->k) * sizeof(double);
+}
+
+extern "C" apr_status apr_conv_bwd_weight(const apr_handle* h, const apr_conv_desc* d, const void* x,
+                                          const void* tree, const float* dy, float* dw, void* ws,
+                                          size_t ws_bytes, void* stream) {
+  apr_status st = check_desc(h, d, "apr_conv_bwd_weight");
+  if (st != APR_OK) return st;
+  if (ws_bytes < apr_conv_bwd_weight_ws(h, d)) APR_FAIL(APR_EINVAL, "apr_conv_bwd_weight: workspace too small");
+  if (!x || !dy || !dw || (h->n_t && !tree) || (apr_conv_bwd_weight_ws(h, d) && !ws))
+    APR_FAIL(APR_EINVAL, "apr_conv_bwd_weight: null buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int cin = d->c_in, cout = d->c_out;
+  double* w64 = static_cast<double*>(ws);
+  if (h->n_p == 0) {
+    const size_t n = size_t(d->n_wlevels) * cin * cout * d->k * d->k * d->k;
+    APR_HIP(hipMemsetAsync(dw, 0, n * sizeof(float), s));
+    return APR_OK;
+  }
+#define APR_WGT(KK, XT)                                                                    \
+  APR_CH_DISPATCH(1, 1, return (bwd_weight_impl<KK, CI, CO, XT>(h, d, x, tree, dy, dw, w64, s))) \
+  APR_CH_DISPATCH(1, 16, return (bwd_weight_impl<KK, CI, CO, XT>(h, d, x, tree, dy, dw, w64, s))) \
+  APR_CH_DISPATCH(16, 16, return (bwd_weight_impl<KK, CI, CO, XT>(h, d, x, tree, dy, dw, w64, s))) \
+  APR_CH_DISPATCH(16, 1, return (bwd_weight_impl<KK, CI, CO, XT>(h, d, x, tree, dy, dw, w64, s))) \
+  APR_CH_DISPATCH(2, 3, return (bwd_weight_impl<KK, CI, CO, XT>(h, d, x, tree, dy, dw, w64, s)))
+  if (d->k == 3 && d->x_dtype == APR_F32) { APR_WGT(3, float) }
+  if (d->k == 3 && d->x_dtype == APR_BF16) { APR_WGT(3, __hip_bfloat16) }
+  if (d->k == 5 && d->x_dtype == APR_F32) {
+    APR_CH_DISPATCH(1, 1, return (bwd_weight_impl<5, CI, CO, float>(h, d, x, tree, dy, dw, w64, s)))
+    APR_CH_DISPATCH(2, 3, return (bwd_weight_impl<5, CI, CO, float>(h, d, x, tree, dy, dw, w64, s)))
+  }
+#undef APR_WGT
+  APR_FAIL(APR_EUNSUPPORTED, "apr_conv_bwd_weight: unsupported (k, c_in, c_out, dtype)");
+}

@@ -1,0 +1,102 @@
+// Richardson-Lucy deconvolution on the APR (Section 6.2): a host loop over
+// the tree-fill and convolution kernels, with the quotient and the update
+// fused into the convolution epilogues.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace apr {
+
+// max |u| over n values: one pass of per-block maxima, then one block
+__global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ u, int64_t n,
+                                                     float* __restrict__ out, int stage) {
+  __shared__ float red[4];
+  float m = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    m = fmaxf(m, fabsf(u[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if (lane_id() == 0) red[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    out[stage == 0 ? blockIdx.x : 0] = m;
+  }
+}
+
+__global__ void scale_kernel(float* __restrict__ v, float s) { v[0] *= s; }
+
+__global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+}  // namespace apr
+
+using namespace apr;
+
+namespace apr {
+apr_status conv_impl(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                     const float* w, void* y, const float* eps_dev, void* stream);
+}
+
+extern "C" size_t apr_richardson_lucy_workspace(const apr_handle* h) {
+  if (!h) return 0;
+  const size_t np = size_t(h->n_p), nt = size_t(h->n_t);
+  return (nt + 3 * np + 1024 + 64) * sizeof(float) + 256;
+}
+
+extern "C" apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_t n_wlevels,
+                                          const float* w, const float* w_flip, const float* u,
+                                          float* out, int32_t n_iter, float eps_rel, void* work,
+                                          void* stream) {
+  if (!h || !w || !w_flip || !u || !out || !work) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: null argument");
+  if (n_iter < 0) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: n_iter < 0");
+  if (out == u) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: out must not alias u");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t np = h->n_p;
+  if (np == 0) return APR_OK;
+  // workspace: tree [N_t] | rho [N_p] | ping [N_p] | pong [N_p] | block maxima | eps
+  char* base = static_cast<char*>(work);
+  base += (256 - (reinterpret_cast<uintptr_t>(base) & 255)) & 255;
+  float* tree = reinterpret_cast<float*>(base);
+  float* rho = tree + h->n_t;
+  float* ping = rho + np;
+  float* pong = ping + np;
+  float* blk = pong + np;
+  float* eps = blk + 1024;
+  const int nblk = int(std::min<int64_t>(1024, (np + 255) / 256));
+  hipLaunchKernelGGL(absmax_kernel, dim3(nblk), dim3(256), 0, s, u, np, blk, 0);
+  hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, blk, int64_t(nblk), eps, 1);
+  hipLaunchKernelGGL(scale_kernel, dim3(1), dim3(1), 0, s, eps, eps_rel);
+  APR_HIP(hipGetLastError());
+
+  apr_conv_desc d{};
+  d.k = k;
+  d.c_in = d.c_out = 1;
+  d.n_wlevels = n_wlevels;
+  d.x_dtype = d.y_dtype = APR_F32;
+  const float* cur = u;   // i_0 = u
+  for (int it = 0; it < n_iter; ++it) {
+    float* nxt = (it == n_iter - 1) ? out : ((cur == ping) ? pong : ping);
+    apr_status st = apr_fill_tree(h, cur, tree, 1, APR_F32, stream);
+    if (st != APR_OK) return st;
+    // rho = u / max(corr(i, w_flip), eps)
+    d.epilogue = APR_EPI_RATIO;
+    d.epi_arg = u;
+    st = conv_impl(h, &d, cur, tree, w_flip, rho, eps, stream);
+    if (st != APR_OK) return st;
+    st = apr_fill_tree(h, rho, tree, 1, APR_F32, stream);
+    if (st != APR_OK) return st;
+    // i <- i * corr(rho, w)
+    d.epilogue = APR_EPI_MUL;
+    d.epi_arg = cur;
+    st = conv_impl(h, &d, rho, tree, w, nxt, nullptr, stream);
+    if (st != APR_OK) return st;
+    cur = nxt;
+  }
+  if (n_iter == 0) {
+    hipLaunchKernelGGL(copy_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, s, u, out, np);
+    APR_HIP(hipGetLastError());
+  }
+  return APR_OK;
+}

@@ -1,0 +1,124 @@
+"""GPU parity of the gather-map path (multichannel convolution) and of the
+hand-written backward kernels, against the FP64 oracle and by the adjoint
+identity / finite differences on the device."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from aprgen.apr_input import CONFIGS, random_apr, sphere_apr
+from oracle import access as A
+from oracle import conv as C
+from oracle.tree import fill_tree as oracle_fill
+from paper_2112_03592_amd import apr as G
+from tests.gpu_common import assert_close_scaled, linear_access
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "rand16_l1": lambda: random_apr((16, 16, 16), l_min=1, seed=2, p_refine=0.25),
+    "rand9x12x7": lambda: random_apr((9, 12, 7), l_min=1, seed=3, p_refine=0.3),
+    "rand33x20x70": lambda: random_apr((33, 20, 70), l_min=2, seed=5, p_refine=0.2),
+    "sphere32": lambda: sphere_apr(CONFIGS["sphere32"]),
+}
+_cache = {}
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def case(name):
+    if name not in _cache:
+        inp = CASES[name]()
+        la = linear_access(inp)
+        _cache[name] = (inp, la, A.tree_structure(la))
+    return _cache[name]
+
+
+def _setup(name, k, cin, cout, nw_shared=False, seed=0):
+    inp, la, tr = case(name)
+    rng = np.random.default_rng(seed)
+    nl = 1 if nw_shared else la.l_max - la.l_min + 1
+    W = rng.normal(size=(nl, cout, cin, k, k, k)).astype(np.float32)
+    x = rng.normal(size=(la.n, cin)).astype(np.float32)
+    return inp, la, tr, W, x
+
+
+CH = [(3, 2, 3), (5, 2, 3), (3, 1, 16), (3, 16, 16), (3, 16, 1), (5, 1, 1), (3, 1, 1)]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("k,cin,cout", CH)
+def test_multichannel_forward(name, k, cin, cout):
+    say("mc fwd", name, k, cin, cout)
+    inp, la, tr, W, x = _setup(name, k, cin, cout, seed=k * 100 + cin * 10 + cout)
+    b = np.random.default_rng(1).normal(size=cout).astype(np.float32)
+    ref = C.apr_conv(la, x.astype(np.float64), W.astype(np.float64), bias=b.astype(np.float64), tree=tr)
+    scale = C.apr_conv(la, np.abs(x.astype(np.float64)), np.abs(W.astype(np.float64)), tree=tr) + np.abs(b)
+    with G.AprAccess.from_input(inp, gather=(k,)) as acc:
+        xd = torch.from_numpy(x).cuda()
+        t = G.fill_tree(acc, xd)
+        wd = torch.from_numpy(W).cuda()
+        bd = torch.from_numpy(b).cuda()
+        y = G.conv(acc, xd, t, wd, k, bias=bd).cpu().numpy()
+        yr = G.conv(acc, xd, t, wd, k, bias=bd, relu=True).cpu().numpy()
+    assert_close_scaled(y, ref, scale, 1e-5, f"{name} k={k} {cin}->{cout}")
+    assert_close_scaled(yr, np.maximum(ref, 0), scale, 1e-5, "relu")
+
+
+def test_multichannel_bf16_storage():
+    inp, la, tr, W, x = _setup("sphere32", 3, 16, 16, seed=3)
+    with G.AprAccess.from_input(inp, gather=(3,)) as acc:
+        xb = torch.from_numpy(x).cuda().to(torch.bfloat16)
+        x64 = xb.float().cpu().numpy().astype(np.float64)
+        ref = C.apr_conv(la, x64, W.astype(np.float64), tree=tr)
+        scale = C.apr_conv(la, np.abs(x64), np.abs(W.astype(np.float64)), tree=tr)
+        t = G.fill_tree(acc, xb)
+        y = G.conv(acc, xb, t, torch.from_numpy(W).cuda(), 3, bias=torch.zeros(16, device="cuda"),
+                   out_dtype=torch.float32).cpu().numpy()
+    assert_close_scaled(y, ref, scale, 1e-2, "bf16 storage 16->16")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("k,cin,cout", CH)
+@pytest.mark.parametrize("shared", [False, True])
+def test_backward_data_and_weight(name, k, cin, cout, shared):
+    say("bwd", name, k, cin, cout, shared)
+    inp, la, tr, W, x = _setup(name, k, cin, cout, nw_shared=shared, seed=7 + k + cin + cout)
+    g = np.random.default_rng(11).normal(size=(la.n, cout)).astype(np.float32)
+    W64, g64, x64 = W.astype(np.float64), g.astype(np.float64), x.astype(np.float64)
+    ref_dx = C.apr_conv_bwd_data(la, g64, W64, tree=tr)
+    sc_dx = C.apr_conv_bwd_data(la, np.abs(g64), np.abs(W64), tree=tr)
+    ref_dw = C.apr_conv_bwd_weight(la, x64, g64, k, n_wlevels=W.shape[0], tree=tr)
+    sc_dw = C.apr_conv_bwd_weight(la, np.abs(x64), np.abs(g64), k, n_wlevels=W.shape[0], tree=tr)
+    with G.AprAccess.from_input(inp, gather=(k,)) as acc:
+        xd = torch.from_numpy(x).cuda()
+        t = G.fill_tree(acc, xd)
+        dx = G.conv_bwd_data(acc, torch.from_numpy(g).cuda(), torch.from_numpy(W).cuda(), k).cpu().numpy()
+        dw = G.conv_bwd_weight(acc, xd, t, torch.from_numpy(g).cuda(), k, W.shape[0], cin, cout).cpu().numpy()
+    assert_close_scaled(dx, ref_dx, sc_dx, 1e-5, f"dX {name} k={k} {cin}->{cout}")
+    assert_close_scaled(dw, ref_dw, sc_dw, 1e-5, f"dW {name} k={k} {cin}->{cout}")
+
+
+@pytest.mark.parametrize("k,cin,cout", [(3, 16, 16), (5, 1, 1), (3, 1, 16)])
+def test_adjoint_identity_on_device(k, cin, cout):
+    """<A v, g> from the device forward equals <v, A^T g> from the device
+    backward (the forward is linear in x: a central difference with any step
+    is exact up to rounding)."""
+    inp, la, tr, W, x = _setup("sphere32", k, cin, cout, seed=5)
+    rng = np.random.default_rng(6)
+    g = rng.normal(size=(la.n, cout)).astype(np.float32)
+    with G.AprAccess.from_input(inp, gather=(k,)) as acc:
+        wd = torch.from_numpy(W).cuda()
+        zb = torch.zeros(cout, device="cuda")
+        v = torch.from_numpy(rng.normal(size=(la.n, cin)).astype(np.float32)).cuda()
+        gd = torch.from_numpy(g).cuda()
+        yp = G.conv(acc, v, G.fill_tree(acc, v), wd, k, bias=zb)
+        vm = -v
+        ym = G.conv(acc, vm, G.fill_tree(acc, vm), wd, k, bias=zb)
+        fd = float(((yp - ym) / 2).double().mul(gd.double()).sum())
+        dx = G.conv_bwd_data(acc, gd, wd, k)
+        an = float(dx.double().mul(v.double()).sum())
+    assert abs(fd - an) <= 1e-5 * (abs(fd) + abs(an))

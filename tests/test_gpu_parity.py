@@ -251,3 +251,19 @@ def test_sphere512_conv_sampled(sphere512, k):
     assert_close_scaled(y[smp], ref, scale, 1e-5, f"sphere512 k={k}")
     src, idx = C.neighbor_map(la, k, smp[:512], tree=tr)
     assert np.array_equal(nm, encode_oracle_map(src, idx))
+
+
+@pytest.mark.parametrize("name,k", [("sphere64", 5), ("rand33x20x70", 3)])
+def test_richardson_lucy_10_iterations(name, k):
+    """APR Richardson-Lucy (10 iterations, restricted Gaussian PSF) against
+    the FP64 oracle."""
+    from oracle.rl import richardson_lucy as oracle_rl
+    inp, la, tr = case(name)
+    psf = S.gaussian_stencil(k, 1.5)
+    u = inp.values.astype(np.float64) + 1.0
+    ref = oracle_rl(la, u, psf, 10)
+    with G.AprAccess.from_input(inp) as acc:
+        got = G.richardson_lucy(acc, torch.from_numpy(u.astype(np.float32)).cuda(), psf, 10).cpu().numpy()
+    rel = np.abs(got - ref) / np.abs(ref)
+    say("rl rel err max", rel.max(), "l2", np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    assert rel.max() < 1e-4
