@@ -148,6 +148,7 @@ apr_status apr_stencil_levels(int32_t mode, int32_t k, int32_t n_filters, const 
 #define APR_EPI_NONE 0
 #define APR_EPI_RATIO 1   /* y = u / max(y, eps)   (Richardson-Lucy quotient, Section 6.2) */
 #define APR_EPI_MUL 2     /* y = y * u             (Richardson-Lucy update) */
+#define APR_EPI_MULPOW 3  /* y = u * max(y, 0)^power (update raised to a power; power 1 is MUL) */
 
 typedef struct {
   int32_t k;             /* stencil side: 3 or 5 */
@@ -161,6 +162,7 @@ typedef struct {
   const float* bias;     /* device FP32 [c_out] or NULL (gather path) */
   int32_t relu;          /* nonzero: y = max(y, 0) after bias and residual (gather path) */
   const void* residual;  /* device [N_p][c_out] of y's dtype added before relu, or NULL */
+  float power;           /* exponent of APR_EPI_MULPOW */
 } apr_conv_desc;
 
 /* y[p] = sum_o w_{l_p}[o] * V_{l_p}(c_p + o) for every particle p, with V_l
@@ -216,17 +218,79 @@ apr_status apr_neighbor_map(const apr_handle* h, int32_t k, const int64_t* parti
 /* Bytes of device workspace apr_richardson_lucy needs for this handle. */
 size_t apr_richardson_lucy_workspace(const apr_handle* h);
 
-/* n_iter iterations of  i <- i * corr(u / max(corr(i, w_flip_l), eps), w_l),
- * i_0 = u, eps = eps_rel * max|u|: the Richardson-Lucy update with both
+/* n_iter iterations of  i <- i * corr(u / max(corr(i, w_flip_l), eps), w_l)^power
+ * with i_0 = init (u when init is NULL) and eps = eps_rel * max|u|.  With
+ * power = 1 this is the Richardson-Lucy update of Section 6.2 with both
  * convolutions replaced by APR convolutions and the PSF restricted to every
- * level (Eq. restrict_stenc).  w and w_flip: device FP32 [n_wlevels][k^3], the
- * per-level PSF and per-level flipped PSF (apr_stencil_levels with flip = 0
- * and 1); u, out: device FP32 [N_p] (out may not alias u); work: device
- * workspace of apr_richardson_lucy_workspace bytes.  Every tree is refilled
- * from the array it belongs to.  Asynchronous. */
+ * level (Eq. restrict_stenc); power > 1 over-relaxes the multiplicative
+ * update (an accelerated variant, not in the paper).  w and w_flip: device
+ * FP32 [n_wlevels][k^3], the per-level PSF and per-level flipped PSF
+ * (apr_stencil_levels with flip = 0 and 1); u, init, out: device FP32 [N_p]
+ * (out may alias neither); work: device workspace of
+ * apr_richardson_lucy_workspace bytes.  Every tree is refilled from the array
+ * it belongs to.  Asynchronous. */
 apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_t n_wlevels, const float* w,
-                               const float* w_flip, const float* u, float* out, int32_t n_iter,
-                               float eps_rel, void* work, void* stream);
+                               const float* w_flip, const float* u, const float* init, float* out,
+                               int32_t n_iter, float eps_rel, float power, void* work, void* stream);
+
+/* ----------------------------------------------------------------------
+ * Learned surrogate support.  Section 7 proposes CNNs made of APR
+ * convolution layers whose filters are learned per resolution level by
+ * back-propagating through the interpolation across levels.  These calls are
+ * the non-convolution pieces of such a network's training and inference:
+ * statistics, normalisation, activation and bias gradients, the loss, the
+ * optimiser step and the per-level weight layout.  Reductions use a fixed
+ * grid with FP64 partials summed in a fixed order (deterministic).
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace of apr_moments / apr_relu_bias_grad (for up to
+ * `channels` channels) / apr_rel_l2. */
+size_t apr_nn_workspace(int32_t channels);
+
+/* stats[0] = mean, stats[1] = population standard deviation (1 when zero) of
+ * v_i = u_i (op 0) or v_i = log(max(u_i, 1)) (op 1) over n values, FP64.
+ * u: device FP32 [n]; stats: device FP64 [2].  Asynchronous. */
+apr_status apr_moments(int32_t op, const float* u, int64_t n, double* stats, void* ws, void* stream);
+
+/* out_i = f_op(a_i, b_i) with (mu, sd) = stats, FP64 arithmetic, a+ = max(a, 1):
+ *   0: (a - mu)/sd     1: (a - b)/sd               2: b + sd*a       3: sd*a
+ *   4: (log a+ - mu)/sd  5: (log a+ - log b+)/sd   6: b*exp(sd*a)    7: sd*a*b
+ * (ops 0-3: additive residual network, 4-7: multiplicative residual).
+ * a, b, out: device FP32 [n] (b unused by ops 0, 3, 4; out may alias a or
+ * b).  Asynchronous. */
+apr_status apr_pointwise(int32_t op, const float* a, const float* b, int64_t n, const double* stats, float* out,
+                         void* stream);
+
+/* dy_pre = dy * [y > 0] (relu != 0) or dy (relu == 0) over rows*c values;
+ * db[j] = sum_p dy_pre[p][j] (FP64 partials) when db != NULL.  y, dy, dy_pre:
+ * device FP32 [rows][c] (dy_pre may alias dy); db: device FP32 [c], c <= 256.
+ * Asynchronous. */
+apr_status apr_relu_bias_grad(const float* y, const float* dy, int64_t rows, int32_t c, int32_t relu,
+                              float* dy_pre, float* db, void* ws, void* stream);
+
+/* out[0] = |a - b|^2 / |b|^2 and out[1] = |b|^2 (FP64; out[0] = |a - b|^2 when
+ * b = 0); when grad != NULL, grad = grad_scale * 2 (a - b) / |b|^2, the
+ * gradient of grad_scale * out[0] with respect to a.  a, b, grad: device FP32
+ * [n]; out: device FP64 [2].  Asynchronous. */
+apr_status apr_rel_l2(const float* a, const float* b, int64_t n, double* out, float* grad, float grad_scale,
+                      void* ws, void* stream);
+
+/* One Adam step (bias-corrected moments, step >= 1) on n parameters:
+ * m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).  Device FP32.
+ * Asynchronous. */
+apr_status apr_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                    float eps, int32_t step, void* stream);
+
+/* Per-level weights from weight sets: set s serves the levels at distance s
+ * from the finest level (l = l_max - s), the last set every coarser level
+ * too (Section 7's per-level filters, tied across images of different depth).
+ * dir 0: out[l - l_min][:] = in[set(l)][:]  (in [n_sets][per_set] ->
+ * out [l_max-l_min+1][per_set]);  dir 1: out[s][:] = sum of in[l - l_min][:]
+ * over the levels of set s in ascending l (the gradient of dir 0).  Device
+ * FP32, in and out must not alias.  Asynchronous. */
+apr_status apr_level_weights(int32_t dir, const float* in, float* out, int64_t per_set, int32_t n_sets,
+                             int32_t l_min, int32_t l_max, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* apr_last_error(void);

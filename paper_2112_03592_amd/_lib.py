@@ -18,12 +18,15 @@ APR_F32, APR_BF16 = 0, 1
 APR_VALIDATE_PARTITION, APR_VALIDATE_BALANCE, APR_BUILD_GATHER3, APR_BUILD_GATHER5 = 1, 2, 4, 8
 APR_MAX_LEVELS = 17
 APR_STENCIL_SAME, APR_STENCIL_RESTRICT, APR_STENCIL_ADAPTIVE = 0, 1, 2
-APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL = 0, 1, 2
+APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL, APR_EPI_MULPOW = 0, 1, 2, 3
 
 EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree", "apr_access_destroy",
             "apr_fill_tree", "apr_stencil_levels", "apr_conv", "apr_neighbor_map",
             "apr_richardson_lucy_workspace", "apr_richardson_lucy", "apr_conv_bwd_data",
-            "apr_conv_bwd_weight_ws", "apr_conv_bwd_weight", "apr_last_error"]
+            "apr_conv_bwd_weight_ws", "apr_conv_bwd_weight", "apr_nn_workspace", "apr_moments",
+            "apr_pointwise", "apr_relu_bias_grad", "apr_rel_l2", "apr_adam", "apr_level_weights",
+            "apr_last_error"]
+_SIZE_RETURNING = ("apr_richardson_lucy_workspace", "apr_conv_bwd_weight_ws", "apr_nn_workspace")
 
 
 class AccessDesc(ctypes.Structure):
@@ -45,7 +48,8 @@ class AccessInfo(ctypes.Structure):
 class ConvDesc(ctypes.Structure):
     _fields_ = [("k", c_int32), ("c_in", c_int32), ("c_out", c_int32), ("n_wlevels", c_int32),
                 ("x_dtype", c_int32), ("y_dtype", c_int32), ("epilogue", c_int32), ("eps", c_float),
-                ("epi_arg", c_void_p), ("bias", c_void_p), ("relu", c_int32), ("residual", c_void_p)]
+                ("epi_arg", c_void_p), ("bias", c_void_p), ("relu", c_int32), ("residual", c_void_p),
+                ("power", c_float)]
 
 
 class AprError(RuntimeError):
@@ -78,17 +82,28 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.apr_richardson_lucy_workspace.argtypes = [c_void_p]
     lib.apr_richardson_lucy_workspace.restype = ctypes.c_size_t
     lib.apr_richardson_lucy.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
-                                        c_int32, c_float, c_void_p, c_void_p]
+                                        c_void_p, c_int32, c_float, c_float, c_void_p, c_void_p]
     lib.apr_conv_bwd_data.argtypes = [c_void_p, POINTER(ConvDesc), c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p]
     lib.apr_conv_bwd_weight_ws.argtypes = [c_void_p, POINTER(ConvDesc)]
     lib.apr_conv_bwd_weight_ws.restype = ctypes.c_size_t
     lib.apr_conv_bwd_weight.argtypes = [c_void_p, POINTER(ConvDesc), c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_void_p, ctypes.c_size_t, c_void_p]
+    lib.apr_nn_workspace.argtypes = [c_int32]
+    lib.apr_nn_workspace.restype = ctypes.c_size_t
+    lib.apr_moments.argtypes = [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+    lib.apr_pointwise.argtypes = [c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+    lib.apr_relu_bias_grad.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p,
+                                       c_void_p, c_void_p]
+    lib.apr_rel_l2.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_float, c_void_p, c_void_p]
+    lib.apr_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_float, c_float,
+                             c_float, c_int32, c_void_p]
+    lib.apr_level_weights.argtypes = [c_int32, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32,
+                                      c_void_p]
     lib.apr_last_error.argtypes = []
     lib.apr_last_error.restype = c_char_p
     for name in EXPORTED:
-        if name not in ("apr_last_error", "apr_richardson_lucy_workspace", "apr_conv_bwd_weight_ws"):
+        if name != "apr_last_error" and name not in _SIZE_RETURNING:
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

@@ -17,7 +17,7 @@ from . import _lib as L
 _DT = {torch.float32: L.APR_F32, torch.bfloat16: L.APR_BF16}
 _MODES = {"same": L.APR_STENCIL_SAME, "restrict": L.APR_STENCIL_RESTRICT,
           "adaptive": L.APR_STENCIL_ADAPTIVE}
-_EPI = {None: L.APR_EPI_NONE, "ratio": L.APR_EPI_RATIO, "mul": L.APR_EPI_MUL}
+_EPI = {None: L.APR_EPI_NONE, "ratio": L.APR_EPI_RATIO, "mul": L.APR_EPI_MUL, "mulpow": L.APR_EPI_MULPOW}
 
 
 def _stream() -> int:
@@ -138,7 +138,7 @@ def stencil_levels(w, mode: str, k: int, l_min: int, l_max: int, flip: bool = Fa
 
 
 def _desc(k, c_in, c_out, nw, x_dtype, y_dtype, epilogue=None, eps=0.0, epi_arg=None, bias=None,
-          relu=False, residual=None) -> L.ConvDesc:
+          relu=False, residual=None, power=1.0) -> L.ConvDesc:
     d = L.ConvDesc()
     d.k, d.c_in, d.c_out, d.n_wlevels = k, c_in, c_out, nw
     d.x_dtype, d.y_dtype = _DT[x_dtype], _DT[y_dtype]
@@ -148,6 +148,7 @@ def _desc(k, c_in, c_out, nw, x_dtype, y_dtype, epilogue=None, eps=0.0, epi_arg=
     d.bias = _ptr(bias) if bias is not None else None
     d.relu = int(bool(relu))
     d.residual = _ptr(residual) if residual is not None else None
+    d.power = float(power)
     return d
 
 
@@ -170,7 +171,7 @@ def conv(acc: AprAccess, x: torch.Tensor, tree: torch.Tensor, w: torch.Tensor, k
          y: Optional[torch.Tensor] = None, out_dtype: Optional[torch.dtype] = None,
          epilogue: Optional[str] = None, epi_arg: Optional[torch.Tensor] = None,
          eps: float = 0.0, bias: Optional[torch.Tensor] = None, relu: bool = False,
-         residual: Optional[torch.Tensor] = None) -> torch.Tensor:
+         residual: Optional[torch.Tensor] = None, power: float = 1.0) -> torch.Tensor:
     """APR convolution (``apr_conv``).  x [N_p] or [N_p, c_in]; w FP32
     [nw, k,k,k] or [nw, c_out, c_in, k,k,k] with nw 1 or the number of levels."""
     nw, cout, cin = _wshape(acc, w, k)
@@ -179,7 +180,7 @@ def conv(acc: AprAccess, x: torch.Tensor, tree: torch.Tensor, w: torch.Tensor, k
     if y is None:
         shape = (acc.n_particles,) if (w.dim() == 4 and x.dim() == 1) else (acc.n_particles, cout)
         y = torch.empty(shape, dtype=out_dtype or x.dtype, device=x.device)
-    d = _desc(k, cin, cout, nw, x.dtype, y.dtype, epilogue, eps, epi_arg, bias, relu, residual)
+    d = _desc(k, cin, cout, nw, x.dtype, y.dtype, epilogue, eps, epi_arg, bias, relu, residual, power)
     L.check(acc._lib.apr_conv(acc.handle, ctypes.byref(d), _ptr(x),
                               _ptr(tree) if tree is not None and tree.numel() else None,
                               _ptr(w), _ptr(y), _stream()))
@@ -224,9 +225,11 @@ def neighbor_map(acc: AprAccess, k: int, particles: torch.Tensor) -> torch.Tenso
 
 
 def richardson_lucy(acc: AprAccess, u: torch.Tensor, psf, n_iter: int, eps_rel: float = 1e-12,
-                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                    out: Optional[torch.Tensor] = None, init: Optional[torch.Tensor] = None,
+                    power: float = 1.0) -> torch.Tensor:
     """APR Richardson-Lucy deconvolution of particle values u (FP32) with the
-    PSF restricted to every level (``apr_richardson_lucy``)."""
+    PSF restricted to every level (``apr_richardson_lucy``), starting from
+    ``init`` (u when None), the update raised to ``power``."""
     psf = np.asarray(psf, np.float64)
     k = psf.shape[-1]
     w = torch.from_numpy(stencil_levels(psf, "restrict", k, acc.l_min, acc.l_max)).to(u.device)
@@ -235,6 +238,98 @@ def richardson_lucy(acc: AprAccess, u: torch.Tensor, psf, n_iter: int, eps_rel: 
     ws = torch.empty(nbytes, dtype=torch.uint8, device=u.device)
     if out is None:
         out = torch.empty_like(u)
-    L.check(acc._lib.apr_richardson_lucy(acc.handle, k, w.shape[0], _ptr(w), _ptr(wf), _ptr(u), _ptr(out),
-                                         int(n_iter), float(eps_rel), _ptr(ws), _stream()))
+    L.check(acc._lib.apr_richardson_lucy(acc.handle, k, w.shape[0], _ptr(w), _ptr(wf), _ptr(u), _ptr(init), _ptr(out),
+                                         int(n_iter), float(eps_rel), float(power), _ptr(ws), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Surrogate network support (apr_moments ... apr_level_weights)
+# ---------------------------------------------------------------------------
+
+class Workspace:
+    """Device scratch of apr_nn_workspace bytes for up to ``channels`` channels."""
+
+    def __init__(self, channels: int = 16, device="cuda"):
+        n = int(L.load().apr_nn_workspace(channels))
+        self.channels = channels
+        self.buf = torch.empty(n, dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+
+def _f32(t: torch.Tensor) -> torch.Tensor:
+    if t.dtype != torch.float32:
+        raise ValueError("expected FP32")
+    return t
+
+
+def moments(u: torch.Tensor, log: bool, ws: Workspace, stats: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Device FP64 [mean, sd] of u or log(max(u, 1)) (``apr_moments``)."""
+    if stats is None:
+        stats = torch.empty(2, dtype=torch.float64, device=u.device)
+    L.check(L.load().apr_moments(int(log), _ptr(_f32(u)), u.numel(), _ptr(stats), ws.ptr, _stream()))
+    return stats
+
+
+def pointwise(op: int, a: torch.Tensor, b: Optional[torch.Tensor], stats: torch.Tensor,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Elementwise map ``op`` of ``apr_pointwise``."""
+    if out is None:
+        out = torch.empty_like(a)
+    if b is not None and b.numel() != a.numel():
+        raise ValueError("a and b differ in size")
+    L.check(L.load().apr_pointwise(int(op), _ptr(_f32(a)), _ptr(b), a.numel(), _ptr(stats), _ptr(out),
+                                   _stream()))
+    return out
+
+
+def relu_bias_grad(y: Optional[torch.Tensor], dy: torch.Tensor, relu: bool, ws: Workspace,
+                   want_db: bool = True, dy_pre: Optional[torch.Tensor] = None):
+    """(dy * [y > 0] or dy, column sums) (``apr_relu_bias_grad``)."""
+    dy2 = dy if dy.dim() == 2 else dy.reshape(-1, 1)
+    c = dy2.shape[1]
+    if c > ws.channels:
+        raise ValueError("workspace too small for this many channels")
+    if dy_pre is None:
+        dy_pre = torch.empty_like(dy2)
+    db = torch.empty(c, dtype=torch.float32, device=dy.device) if want_db else None
+    L.check(L.load().apr_relu_bias_grad(_ptr(y) if relu else None, _ptr(_f32(dy2)), dy2.shape[0], c, int(relu),
+                                        _ptr(dy_pre), _ptr(db), ws.ptr, _stream()))
+    return dy_pre, db
+
+
+def rel_l2(a: torch.Tensor, b: torch.Tensor, ws: Workspace, grad: bool = False, grad_scale: float = 1.0,
+           out: Optional[torch.Tensor] = None):
+    """(device FP64 [|a-b|^2/|b|^2, |b|^2], gradient or None) (``apr_rel_l2``)."""
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=a.device)
+    g = torch.empty_like(a) if grad else None
+    L.check(L.load().apr_rel_l2(_ptr(_f32(a)), _ptr(_f32(b)), a.numel(), _ptr(out), _ptr(g), float(grad_scale),
+                                ws.ptr, _stream()))
+    return out, g
+
+
+def adam(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+         beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    """In-place Adam step on p (``apr_adam``)."""
+    L.check(L.load().apr_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), float(lr), float(beta1),
+                              float(beta2), float(eps), int(step), _stream()))
+
+
+def level_weights(P: torch.Tensor, l_min: int, l_max: int) -> torch.Tensor:
+    """Per-level weights [l_max-l_min+1, ...] from weight sets P [n_sets, ...]."""
+    out = torch.empty((l_max - l_min + 1,) + tuple(P.shape[1:]), dtype=torch.float32, device=P.device)
+    L.check(L.load().apr_level_weights(0, _ptr(_f32(P)), _ptr(out), P[0].numel(), P.shape[0], l_min, l_max,
+                                       _stream()))
+    return out
+
+
+def fold_level_weights(G: torch.Tensor, n_sets: int, l_min: int, l_max: int) -> torch.Tensor:
+    """Gradient of ``level_weights``: per-set sums of the per-level rows of G."""
+    out = torch.empty((n_sets,) + tuple(G.shape[1:]), dtype=torch.float32, device=G.device)
+    L.check(L.load().apr_level_weights(1, _ptr(_f32(G)), _ptr(out), G[0].numel(), n_sets, l_min, l_max,
+                                       _stream()))
     return out

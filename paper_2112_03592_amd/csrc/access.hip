@@ -313,6 +313,7 @@ __global__ void tile_compact_kernel(TileLevels tl, const uint32_t* __restrict__ 
 // Host side
 // ---------------------------------------------------------------------------
 apr_status build_gather_map(const apr_handle* h, int k, int32_t* map32, hipStream_t s);
+apr_status build_child_map(const apr_handle* h, uint32_t* cmap, hipStream_t s);
 
 static int finest_level(const int32_t* dims) {
   int32_t mx = std::max(dims[0], std::max(dims[1], dims[2]));
@@ -593,6 +594,11 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
     }
     APR_TRY(dev_alloc(h, &h->gmap[gi], h->n_p * int64_t(k * k * k)));
     APR_TRY(build_gather_map(h, k, h->gmap[gi], s));
+  }
+  // ---- child map of the tree nodes (fill of many channels)
+  if ((h->gmap[0] || h->gmap[1]) && h->n_t > 0) {
+    APR_TRY(dev_alloc(h, &h->cmap, h->n_t * 8));
+    APR_TRY(build_child_map(h, h->cmap, s));
   }
   APR_TRY_HIP(hipStreamSynchronize(s));
   for (void* p : tmp) (void)hipFree(p);

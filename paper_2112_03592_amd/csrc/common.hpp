@@ -73,6 +73,39 @@ template <> __device__ inline __hip_bfloat16 from_f32<__hip_bfloat16>(float v) {
   return __float2bfloat16(v);   // round to nearest even
 }
 
+// CH values of a row at p (16-byte aligned when CH * sizeof(T) is a multiple
+// of 16: vector loads/stores), converted to/from FP32
+template <typename T, int CH>
+__device__ inline void load_vec(const T* p, float* v) {
+  constexpr int kB = CH * int(sizeof(T));
+  if constexpr (kB % 16 == 0) {
+    uint4 raw[kB / 16];
+#pragma unroll
+    for (int i = 0; i < kB / 16; ++i) raw[i] = reinterpret_cast<const uint4*>(p)[i];
+    T t[CH];
+    __builtin_memcpy(t, raw, kB);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) v[c] = to_f32<T>(t[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) v[c] = to_f32<T>(p[c]);
+  }
+}
+
+template <typename T, int CH>
+__device__ inline void store_vec(T* p, const T* t) {
+  constexpr int kB = CH * int(sizeof(T));
+  if constexpr (kB % 16 == 0) {
+    uint4 raw[kB / 16];
+    __builtin_memcpy(raw, t, kB);
+#pragma unroll
+    for (int i = 0; i < kB / 16; ++i) reinterpret_cast<uint4*>(p)[i] = raw[i];
+  } else {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) p[c] = t[c];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side state and error reporting
 // ---------------------------------------------------------------------------
@@ -112,6 +145,7 @@ struct apr_handle {
   uint64_t* tiles = nullptr;  // conv tiles [n_tiles], finest level first
   int64_t n_tiles = 0;
   int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]
+  uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t] (with the gather maps)
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
 };

@@ -48,6 +48,7 @@ struct ConvArgs {
   int32_t epi;
   float eps;
   const float* eps_dev;   // when set, the ratio clamp is read from device memory
+  float power;            // exponent of APR_EPI_MULPOW
   const void* epi_arg;
   const int64_t* sel;   // neighbour-map mode: sorted particle list
   int64_t n_sel;
@@ -454,6 +455,8 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
           acc = u / fmaxf(acc, a.eps_dev ? *a.eps_dev : a.eps);
         } else if (a.epi == APR_EPI_MUL) {
           acc *= to_f32<TY>(static_cast<const TY*>(a.epi_arg)[idx]);
+        } else if (a.epi == APR_EPI_MULPOW) {
+          acc = to_f32<TY>(static_cast<const TY*>(a.epi_arg)[idx]) * powf(fmaxf(acc, 0.f), a.power);
         }
         yo[idx] = from_f32<TY>(acc);
       }
@@ -518,7 +521,7 @@ apr_status apr::conv_impl(const apr_handle* h, const apr_conv_desc* d, const voi
   const int nl = h->meta.l_max - h->meta.l_min + 1;
   if (d->n_wlevels != 1 && d->n_wlevels != nl)
     APR_FAIL(APR_EINVAL, "apr_conv: n_wlevels must be 1 or l_max - l_min + 1");
-  if (d->epilogue < APR_EPI_NONE || d->epilogue > APR_EPI_MUL)
+  if (d->epilogue < APR_EPI_NONE || d->epilogue > APR_EPI_MULPOW)
     APR_FAIL(APR_EINVAL, "apr_conv: unknown epilogue");
   if (h->n_p == 0 || h->n_tiles == 0) return APR_OK;
   if (!x || !w || !y || (h->n_t && !tree)) APR_FAIL(APR_EINVAL, "apr_conv: null buffer");
@@ -537,6 +540,7 @@ apr_status apr::conv_impl(const apr_handle* h, const apr_conv_desc* d, const voi
   a.epi = d->epilogue;
   a.eps = d->eps;
   a.eps_dev = eps_dev;
+  a.power = d->power;
   a.epi_arg = d->epi_arg;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return d->k == 3 ? launch_conv<3, false>(a, d->x_dtype, d->y_dtype, s)

@@ -337,6 +337,99 @@ static const int32_t* gather_map(const apr_handle* h, int k) { return h->gmap[k 
     __VA_ARGS__;                                                                     \
   }
 
+// ---------------------------------------------------------------------------
+// Multichannel forward, 16 -> 16 channels, BF16 activations, on MFMA
+// (v_mfma_f32_16x16x16_bf16: 16 particles x 16 input channels times 16 input
+// x 16 output channels per tap, 27 taps accumulated in FP32).  Lane l holds
+// A[m = l % 16][k = 4 (l / 16) + i], B[k = 4 (l / 16) + i][n = l % 16] and
+// D[m = 4 (l / 16) + i][n = l % 16], i = 0..3.  The per-level weights of
+// every tap stay in registers as BF16 (B operands); a wave walks 16-particle
+// tiles of one level, the blocks mapped so that each XCD takes a contiguous
+// run of tiles (neighbouring tiles share gathered rows in that XCD's L2).
+// ---------------------------------------------------------------------------
+typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_bits(float v) {
+  const __hip_bfloat16 b = from_f32<__hip_bfloat16>(v);
+  short r;
+  __builtin_memcpy(&r, &b, 2);
+  return r;
+}
+
+constexpr int kMfmaWaves = 4;
+constexpr int kMfmaTiles = 4;   // 16-particle tiles per wave
+
+template <typename TY>
+__global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma_kernel(
+    const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end,
+    const __hip_bfloat16* __restrict__ x, const __hip_bfloat16* __restrict__ tree, const float* __restrict__ w_level,
+    const float* __restrict__ bias, int relu, const TY* __restrict__ residual, TY* __restrict__ y,
+    uint32_t n_blocks) {
+  constexpr int K3 = 27;
+  const uint32_t per_xcd = gridDim.x / 8;
+  const uint32_t blk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (blk >= n_blocks) return;
+  const int lane = int(threadIdx.x & 63);
+  const int r16 = lane & 15, kg = lane >> 4;
+  mfma_s4 bw[K3];
+#pragma unroll
+  for (int q = 0; q < K3; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bw[q][i] = bf16_bits(w_level[(r16 * 16 + 4 * kg + i) * K3 + q]);
+  const float bco = bias ? bias[r16] : 0.f;
+  for (int t = 0; t < kMfmaTiles; ++t) {
+    const uint32_t tile = (blk * kMfmaWaves + threadIdx.x / 64) * kMfmaTiles + t;
+    const uint32_t t0 = p_begin + tile * 16;
+    if (t0 >= p_end) return;
+    const uint32_t p = t0 + r16;
+    const bool valid = p < p_end;
+    uint32_t g[K3];
+#pragma unroll
+    for (int q = 0; q < K3; ++q) g[q] = valid ? gmap[size_t(q) * size_t(n_p) + p] : kPad;
+    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < K3; ++q) {
+      mfma_s4 a = {0, 0, 0, 0};
+      if (g[q] != kPad) {
+        const __hip_bfloat16* src = ((g[q] >> 30) == 3 ? tree : x) + size_t(g[q] & kIdxMask) * 16 + 4 * kg;
+        a = *reinterpret_cast<const mfma_s4*>(src);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[q], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t pm = t0 + 4 * kg + i;
+      if (pm >= p_end) continue;
+      float o = acc[i] + bco;
+      if (residual) o += to_f32<TY>(residual[size_t(pm) * 16 + r16]);
+      if (relu) o = fmaxf(o, 0.f);
+      y[size_t(pm) * 16 + r16] = from_f32<TY>(o);
+    }
+  }
+}
+
+template <typename TY>
+static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                             const float* w, void* y, hipStream_t s) {
+  const Meta& m = h->meta;
+  uint32_t begin = 0;
+  for (int l = m.l_min; l <= m.l_max; ++l) {
+    const uint32_t np_l = uint32_t(h->per_level_p[l]);
+    if (np_l) {
+      const float* wl = w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * 16 * 16 * 27;
+      const uint32_t tiles = (np_l + 15) / 16;
+      const uint32_t nb = (tiles + kMfmaWaves * kMfmaTiles - 1) / (kMfmaWaves * kMfmaTiles);
+      const uint32_t grid = (nb + 7) / 8 * 8;
+      hipLaunchKernelGGL((mc16_mfma_kernel<TY>), dim3(grid), dim3(64 * kMfmaWaves), 0, s,
+                         reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p, begin, begin + np_l,
+                         static_cast<const __hip_bfloat16*>(x), static_cast<const __hip_bfloat16*>(tree), wl,
+                         d->bias, d->relu, static_cast<const TY*>(d->residual), static_cast<TY*>(y), nb);
+    }
+    begin += np_l;
+  }
+}
+
 template <int K, int CI, int CO, typename TX, typename TY>
 static void launch_mc_fwd(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                           const float* w, void* y, hipStream_t s) {
@@ -375,6 +468,15 @@ apr_status mc_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, c
     APR_FAIL(APR_EINVAL, "apr_conv: this path needs the gather map; build the access with "
                          "APR_BUILD_GATHER3 / APR_BUILD_GATHER5");
   const int cin = d->c_in, cout = d->c_out;
+  if (d->k == 3 && cin == 16 && cout == 16 && d->x_dtype == APR_BF16 &&
+      ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 7) == 0) {
+    if (d->y_dtype == APR_BF16)
+      launch_mc16_mfma<__hip_bfloat16>(h, d, x, tree, w, y, s);
+    else
+      launch_mc16_mfma<float>(h, d, x, tree, w, y, s);
+    APR_HIP(hipGetLastError());
+    return APR_OK;
+  }
   if (d->k == 3) {
     APR_CH_DISPATCH(1, 1, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
     APR_CH_DISPATCH(1, 16, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))

@@ -47,11 +47,13 @@ extern "C" size_t apr_richardson_lucy_workspace(const apr_handle* h) {
 
 extern "C" apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_t n_wlevels,
                                           const float* w, const float* w_flip, const float* u,
-                                          float* out, int32_t n_iter, float eps_rel, void* work,
-                                          void* stream) {
+                                          const float* init, float* out, int32_t n_iter, float eps_rel,
+                                          float power, void* work, void* stream) {
   if (!h || !w || !w_flip || !u || !out || !work) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: null argument");
   if (n_iter < 0) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: n_iter < 0");
-  if (out == u) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: out must not alias u");
+  if (!(power > 0.f) || !(power < 16.f)) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: power must be in (0, 16)");
+  if (out == u || (init && out == init))
+    APR_FAIL(APR_EINVAL, "apr_richardson_lucy: out must not alias u or init");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t np = h->n_p;
   if (np == 0) return APR_OK;
@@ -75,7 +77,8 @@ extern "C" apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_
   d.c_in = d.c_out = 1;
   d.n_wlevels = n_wlevels;
   d.x_dtype = d.y_dtype = APR_F32;
-  const float* cur = u;   // i_0 = u
+  const float* i0 = init ? init : u;
+  const float* cur = i0;
   for (int it = 0; it < n_iter; ++it) {
     float* nxt = (it == n_iter - 1) ? out : ((cur == ping) ? pong : ping);
     apr_status st = apr_fill_tree(h, cur, tree, 1, APR_F32, stream);
@@ -87,15 +90,16 @@ extern "C" apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_
     if (st != APR_OK) return st;
     st = apr_fill_tree(h, rho, tree, 1, APR_F32, stream);
     if (st != APR_OK) return st;
-    // i <- i * corr(rho, w)
-    d.epilogue = APR_EPI_MUL;
+    // i <- i * corr(rho, w)   (or i * corr(rho, w)^power)
+    d.epilogue = power == 1.f ? APR_EPI_MUL : APR_EPI_MULPOW;
+    d.power = power;
     d.epi_arg = cur;
     st = conv_impl(h, &d, rho, tree, w, nxt, nullptr, stream);
     if (st != APR_OK) return st;
     cur = nxt;
   }
   if (n_iter == 0) {
-    hipLaunchKernelGGL(copy_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, s, u, out, np);
+    hipLaunchKernelGGL(copy_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, s, i0, out, np);
     APR_HIP(hipGetLastError());
   }
   return APR_OK;

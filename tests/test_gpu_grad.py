@@ -122,3 +122,58 @@ def test_adjoint_identity_on_device(k, cin, cout):
         dx = G.conv_bwd_data(acc, gd, wd, k)
         an = float(dx.double().mul(v.double()).sum())
     assert abs(fd - an) <= 1e-5 * (abs(fd) + abs(an))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_fill_16_channels_via_child_map_equals_one_channel_fill(name, dtype):
+    """The 16-channel fill (child map, built with the gather maps) sums the
+    children in the one-channel kernel's order: bit-identical per channel."""
+    inp, la, tr = case(name)
+    x = np.random.default_rng(4).normal(size=(la.n, 16)).astype(np.float32)
+    with G.AprAccess.from_input(inp, gather=(3,)) as acc:
+        xd = torch.from_numpy(x).cuda().to(dtype)
+        t16 = G.fill_tree(acc, xd).cpu()
+        for c in (0, 7, 15):
+            t1 = G.fill_tree(acc, xd[:, c].contiguous()).cpu()
+            assert torch.equal(t16[:, c], t1), c
+    ref = oracle_fill(la, tr, xd.float().cpu().numpy().astype(np.float64))
+    assert np.allclose(t16.float().numpy(), ref, rtol=1e-6 if dtype == torch.float32 else 1e-2, atol=1e-6)
+
+
+def _bf16_round(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).float().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("out_dtype", [torch.float32, torch.bfloat16])
+def test_mfma_16x16_forward(name, out_dtype):
+    """16 -> 16 channels with BF16 activations runs on MFMA with BF16 weights
+    and FP32 accumulation: against the oracle on the BF16-rounded inputs and
+    weights only the summation order differs."""
+    say("mfma", name, out_dtype)
+    inp, la, tr, W, x = _setup(name, 3, 16, 16, seed=21)
+    rng = np.random.default_rng(22)
+    b = rng.normal(size=16).astype(np.float32)
+    res = rng.normal(size=(la.n, 16)).astype(np.float32)
+    xb, Wb = _bf16_round(x).astype(np.float64), _bf16_round(W).astype(np.float64)
+    resb = _bf16_round(res).astype(np.float64) if out_dtype == torch.bfloat16 else res.astype(np.float64)
+    # tree values are stored in BF16 too: the oracle's means, rounded
+    tv = _bf16_round(oracle_fill(la, tr, xb)).astype(np.float64)
+    ref = C.apr_conv(la, xb, Wb, bias=b.astype(np.float64), tree=tr, tvals=tv)
+    scale = C.apr_conv(la, np.abs(xb), np.abs(Wb), tree=tr, tvals=np.abs(tv)) + np.abs(b)
+    with G.AprAccess.from_input(inp, gather=(3,)) as acc:
+        xd = torch.from_numpy(x).cuda().to(torch.bfloat16)
+        t = G.fill_tree(acc, xd)
+        wd = torch.from_numpy(W).cuda()
+        bd = torch.from_numpy(b).cuda()
+        rd = torch.from_numpy(res).cuda().to(out_dtype)
+        y = G.conv(acc, xd, t, wd, 3, bias=bd, out_dtype=out_dtype).float().cpu().numpy()
+        yr = G.conv(acc, xd, t, wd, 3, bias=bd, relu=True, residual=rd, out_dtype=out_dtype).float().cpu().numpy()
+    tol = 2e-5 if out_dtype == torch.float32 else 8e-3
+    for got, want, sc, what in ((y, ref, scale, "plain"), (yr, np.maximum(ref + resb, 0), scale + np.abs(resb), "relu")):
+        r = np.abs(got - want) / np.maximum(sc, 1e-30)
+        # a tree mean rounded once from FP64 and once from FP32 can differ by
+        # one BF16 unit in rare ties: allow it on at most 0.1% of the outputs
+        assert r.max() < 5e-3, (what, name, r.max())
+        assert (r > tol).mean() < 1e-3, (what, name, (r > tol).mean(), r.max())

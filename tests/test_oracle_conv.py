@@ -276,3 +276,37 @@ def test_rl_with_identity_psf_returns_input():
     d[1, 1, 1] = 1.0
     u = inp.values.astype(np.float64)
     assert np.allclose(richardson_lucy(la, u, d, 3), u, rtol=1e-14)
+
+
+def test_rl_identity_psf_from_init_closed_form():
+    """With a delta PSF one step from i_0 = s gives s * (u / s)^power, and
+    the all-finest power step equals the pixel recursion."""
+    inp = random_apr((16, 16, 16), l_min=1, seed=4)
+    la = _la(inp)
+    d = np.zeros((3, 3, 3))
+    d[1, 1, 1] = 1.0
+    rng = np.random.default_rng(8)
+    u = rng.uniform(50, 500, la.n)
+    s = rng.uniform(50, 500, la.n)
+    for p in (1.0, 1.7, 2.5):
+        got = richardson_lucy(la, u, d, 1, init=s, power=p)
+        assert np.allclose(got, s * (u / s) ** p, rtol=1e-12)
+
+
+def test_rl_power_all_finest_equals_pixel_recursion():
+    dims = (9, 8, 10)
+    rng = np.random.default_rng(9)
+    img = rng.uniform(50, 150, size=dims)
+    inp = dense_apr(dims, l_min=0, values=img.reshape(-1))
+    la = _la(inp)
+    psf = gaussian_stencil(5, 1.5)
+    psf[1, 0, 2] += 0.02
+    psf /= psf.sum()
+    got = richardson_lucy(la, inp.values.astype(np.float64), psf, 3, power=2.2)
+    u = inp.values.astype(np.float64).reshape(dims)
+    i = u.copy()
+    eps = 1e-12 * np.abs(u).max()
+    for _ in range(3):
+        rho = u / np.maximum(ndimage.convolve(i, psf, mode="constant", cval=0.0), eps)
+        i = i * ndimage.correlate(rho, psf, mode="constant", cval=0.0) ** 2.2
+    assert np.allclose(got, i.reshape(-1), rtol=1e-11)
