@@ -15,6 +15,7 @@
 //                per-block FP32 sums, FP64 partials, fixed-order FP64 reduce.
 // Every output has a single writer and a fixed summation order: results are
 // deterministic.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.hpp"
@@ -43,46 +44,75 @@ __device__ inline void load_row(const T* base, int C, float* v) {
 }
 
 // ---------------------------------------------------------------------------
-// Multichannel forward: one wave per particle row of level l, one lane per
-// particle.  Weights of level l are uniform (scalar loads).
+// Multichannel forward on the vector ALUs: one lane per particle of level l
+// (flat over the level's particles, blocks mapped so that each XCD takes a
+// contiguous run).  The gather-map entries of a chunk of taps are all loaded
+// before the first row load (independent loads in flight); the level's
+// weights sit in LDS as [tap][c_in][c_out] (same address in every lane:
+// broadcast reads).
 // ---------------------------------------------------------------------------
+constexpr int kFlatThreads = 256;
+
+template <int K, int CIN, int COUT>
+struct FlatCfg {
+  static constexpr int K3 = K * K * K;
+  static constexpr int NW = K3 * CIN * COUT;
+  static constexpr int CHUNK = K3 <= 27 ? K3 : 25;   // taps whose map entries are loaded together
+};
+
+// first block of the contiguous run given to XCD blockIdx % 8
+__device__ inline uint32_t xcd_block(uint32_t n_blocks) {
+  const uint32_t per_xcd = gridDim.x / 8;
+  const uint32_t blk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  return blk < n_blocks ? blk : 0xffffffffu;
+}
+
 template <int K, int CIN, int COUT, typename TX, typename TY>
-__global__ __launch_bounds__(64 * kGWaves) void mc_fwd_kernel(
-    Meta m, int l, const uint32_t* __restrict__ pend, const int32_t* __restrict__ gmap, int64_t n_p,
-    const TX* __restrict__ x, const TX* __restrict__ tree, const float* w_level,
-    const float* bias, int relu, const TY* __restrict__ residual, TY* __restrict__ y) {
-  constexpr int K3 = K * K * K;
-  const int64_t row = int64_t(blockIdx.x) * kGWaves + threadIdx.x / 64;
-  if (row >= int64_t(m.dz[l]) * m.dx[l]) return;
-  uint32_t b, e;
-  row_range(pend, m.prow[l] + uint32_t(row), b, e);
-  cfloat* W = as_const(w_level);
-  cfloat* B = bias ? as_const(bias) : nullptr;
-  for (uint32_t p = b + lane_id(); p < e; p += 64) {
-    float acc[COUT];
+__global__ __launch_bounds__(kFlatThreads) void mc_fwd_kernel(
+    const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end, const TX* __restrict__ x,
+    const TX* __restrict__ tree, const float* __restrict__ w_level, const float* __restrict__ bias, int relu,
+    const TY* __restrict__ residual, TY* __restrict__ y, uint32_t n_blocks) {
+  using Cfg = FlatCfg<K, CIN, COUT>;
+  constexpr int K3 = Cfg::K3, CHUNK = Cfg::CHUNK;
+  __shared__ float sw[Cfg::NW];
+  for (int i = threadIdx.x; i < Cfg::NW; i += kFlatThreads) {
+    const int q = i % K3, ci = (i / K3) % CIN, co = i / (K3 * CIN);   // source layout [co][ci][q]
+    sw[(q * CIN + ci) * COUT + co] = w_level[i];
+  }
+  __syncthreads();
+  const uint32_t blk = xcd_block(n_blocks);
+  if (blk == 0xffffffffu) return;
+  const uint32_t p = p_begin + blk * kFlatThreads + threadIdx.x;
+  if (p >= p_end) return;
+  float acc[COUT];
 #pragma unroll
-    for (int co = 0; co < COUT; ++co) acc[co] = B ? B[co] : 0.f;
-#pragma unroll 1
-    for (int q = 0; q < K3; ++q) {
-      const uint32_t g = gmap[size_t(q) * size_t(n_p) + p];
-      if (g == kPad) continue;
-      const uint32_t idx = g & kIdxMask;
-      const TX* src = ((g >> 30) == 3) ? tree + size_t(idx) * CIN : x + size_t(idx) * CIN;
+  for (int co = 0; co < COUT; ++co) acc[co] = bias ? bias[co] : 0.f;
+  for (int q0 = 0; q0 < K3; q0 += CHUNK) {
+    uint32_t g[CHUNK];
+#pragma unroll
+    for (int j = 0; j < CHUNK; ++j) g[j] = (q0 + j < K3) ? gmap[size_t(q0 + j) * size_t(n_p) + p] : kPad;
+#pragma unroll
+    for (int j = 0; j < CHUNK; ++j) {
+      if (g[j] == kPad) continue;
+      const TX* src = (((g[j] >> 30) == 3) ? tree : x) + size_t(g[j] & kIdxMask) * CIN;
       float v[CIN];
-      load_row<TX>(src, CIN, v);
+      load_vec<TX, CIN>(src, v);
+      const float* wq = sw + (q0 + j) * CIN * COUT;
 #pragma unroll
-      for (int co = 0; co < COUT; ++co)
+      for (int ci = 0; ci < CIN; ++ci)
 #pragma unroll
-        for (int ci = 0; ci < CIN; ++ci) acc[co] = fmaf(W[(co * CIN + ci) * K3 + q], v[ci], acc[co]);
-    }
-#pragma unroll
-    for (int co = 0; co < COUT; ++co) {
-      float o = acc[co];
-      if (residual) o += to_f32<TY>(residual[size_t(p) * COUT + co]);
-      if (relu) o = fmaxf(o, 0.f);
-      y[size_t(p) * COUT + co] = from_f32<TY>(o);
+        for (int co = 0; co < COUT; ++co) acc[co] = fmaf(wq[ci * COUT + co], v[ci], acc[co]);
     }
   }
+  TY out[COUT];
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) {
+    float o = acc[co];
+    if (residual) o += to_f32<TY>(residual[size_t(p) * COUT + co]);
+    if (relu) o = fmaxf(o, 0.f);
+    out[co] = from_f32<TY>(o);
+  }
+  store_vec<TY, COUT>(y + size_t(p) * COUT, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,18 +388,23 @@ __device__ inline short bf16_bits(float v) {
 }
 
 constexpr int kMfmaWaves = 4;
-constexpr int kMfmaTiles = 4;   // 16-particle tiles per wave
+constexpr int kMfmaBlocksPerXcd = 96;   // 32 CUs x 12 waves / 4 waves per block
 
 template <typename TY>
 __global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma_kernel(
     const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end,
     const __hip_bfloat16* __restrict__ x, const __hip_bfloat16* __restrict__ tree, const float* __restrict__ w_level,
-    const float* __restrict__ bias, int relu, const TY* __restrict__ residual, TY* __restrict__ y,
-    uint32_t n_blocks) {
+    const float* __restrict__ bias, int relu, const TY* __restrict__ residual, TY* __restrict__ y) {
   constexpr int K3 = 27;
-  const uint32_t per_xcd = gridDim.x / 8;
-  const uint32_t blk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (blk >= n_blocks) return;
+  // XCD blockIdx % 8 takes the contiguous tile range [tb, te); its waves
+  // stride through it
+  const uint32_t n_tiles = (p_end - p_begin + 15) / 16;
+  const uint32_t per = (n_tiles + 7) / 8;
+  const uint32_t tb = (blockIdx.x % 8) * per;
+  const uint32_t te = min(n_tiles, tb + per);
+  const uint32_t waves_per_xcd = (gridDim.x / 8) * kMfmaWaves;
+  uint32_t tile = tb + (blockIdx.x / 8) * kMfmaWaves + threadIdx.x / 64;
+  if (tile >= te) return;
   const int lane = int(threadIdx.x & 63);
   const int r16 = lane & 15, kg = lane >> 4;
   mfma_s4 bw[K3];
@@ -378,25 +413,24 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma_kernel(
 #pragma unroll
     for (int i = 0; i < 4; ++i) bw[q][i] = bf16_bits(w_level[(r16 * 16 + 4 * kg + i) * K3 + q]);
   const float bco = bias ? bias[r16] : 0.f;
-  for (int t = 0; t < kMfmaTiles; ++t) {
-    const uint32_t tile = (blk * kMfmaWaves + threadIdx.x / 64) * kMfmaTiles + t;
+  for (; tile < te; tile += waves_per_xcd) {
     const uint32_t t0 = p_begin + tile * 16;
-    if (t0 >= p_end) return;
     const uint32_t p = t0 + r16;
     const bool valid = p < p_end;
     uint32_t g[K3];
 #pragma unroll
     for (int q = 0; q < K3; ++q) g[q] = valid ? gmap[size_t(q) * size_t(n_p) + p] : kPad;
-    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+    mfma_s4 a[K3];
 #pragma unroll
     for (int q = 0; q < K3; ++q) {
-      mfma_s4 a = {0, 0, 0, 0};
-      if (g[q] != kPad) {
-        const __hip_bfloat16* src = ((g[q] >> 30) == 3 ? tree : x) + size_t(g[q] & kIdxMask) * 16 + 4 * kg;
-        a = *reinterpret_cast<const mfma_s4*>(src);
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[q], acc, 0, 0, 0);
+      a[q] = mfma_s4{0, 0, 0, 0};
+      if (g[q] != kPad)
+        a[q] = *reinterpret_cast<const mfma_s4*>(((g[q] >> 30) == 3 ? tree : x) + size_t(g[q] & kIdxMask) * 16 +
+                                                 4 * kg);
     }
+    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < K3; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], bw[q], acc, 0, 0, 0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t pm = t0 + 4 * kg + i;
@@ -419,12 +453,13 @@ static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const 
     if (np_l) {
       const float* wl = w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * 16 * 16 * 27;
       const uint32_t tiles = (np_l + 15) / 16;
-      const uint32_t nb = (tiles + kMfmaWaves * kMfmaTiles - 1) / (kMfmaWaves * kMfmaTiles);
-      const uint32_t grid = (nb + 7) / 8 * 8;
-      hipLaunchKernelGGL((mc16_mfma_kernel<TY>), dim3(grid), dim3(64 * kMfmaWaves), 0, s,
-                         reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p, begin, begin + np_l,
-                         static_cast<const __hip_bfloat16*>(x), static_cast<const __hip_bfloat16*>(tree), wl,
-                         d->bias, d->relu, static_cast<const TY*>(d->residual), static_cast<TY*>(y), nb);
+      // enough waves to fill every CU (3 per SIMD), no more than one per tile
+      const uint32_t blocks_per_xcd = std::min<uint32_t>(kMfmaBlocksPerXcd, (tiles / 8 + kMfmaWaves) / kMfmaWaves);
+      hipLaunchKernelGGL((mc16_mfma_kernel<TY>), dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)),
+                         dim3(64 * kMfmaWaves), 0, s, reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p,
+                         begin, begin + np_l, static_cast<const __hip_bfloat16*>(x),
+                         static_cast<const __hip_bfloat16*>(tree), wl, d->bias, d->relu,
+                         static_cast<const TY*>(d->residual), static_cast<TY*>(y));
     }
     begin += np_l;
   }
@@ -434,14 +469,18 @@ template <int K, int CI, int CO, typename TX, typename TY>
 static void launch_mc_fwd(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                           const float* w, void* y, hipStream_t s) {
   const Meta& m = h->meta;
+  uint32_t begin = 0;
   for (int l = m.l_min; l <= m.l_max; ++l) {
-    if (!h->per_level_p[l]) continue;
-    const int64_t rows = int64_t(m.dz[l]) * m.dx[l];
-    const float* wl = w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * CO * CI * K * K * K;
-    hipLaunchKernelGGL((mc_fwd_kernel<K, CI, CO, TX, TY>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
-                       dim3(64 * kGWaves), 0, s, m, l, h->pend, gather_map(h, K), h->n_p,
-                       static_cast<const TX*>(x), static_cast<const TX*>(tree), wl, d->bias, d->relu,
-                       static_cast<const TY*>(d->residual), static_cast<TY*>(y));
+    const uint32_t np_l = uint32_t(h->per_level_p[l]);
+    if (np_l) {
+      const float* wl = w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * CO * CI * K * K * K;
+      const uint32_t nb = (np_l + kFlatThreads - 1) / kFlatThreads;
+      hipLaunchKernelGGL((mc_fwd_kernel<K, CI, CO, TX, TY>), dim3((nb + 7) / 8 * 8), dim3(kFlatThreads), 0, s,
+                         reinterpret_cast<const uint32_t*>(gather_map(h, K)), h->n_p, begin, begin + np_l,
+                         static_cast<const TX*>(x), static_cast<const TX*>(tree), wl, d->bias, d->relu,
+                         static_cast<const TY*>(d->residual), static_cast<TY*>(y), nb);
+    }
+    begin += np_l;
   }
 }
 
