@@ -434,3 +434,41 @@ def gaussian_stencil(k: int, sigma: float) -> np.ndarray:
     g = np.exp(-0.5 * (t / sigma) ** 2)
     g = g / g.sum()
     return np.einsum("i,j,k->ijk", g, g, g)
+
+
+# ----------------------------------------------------------------------------
+# Deconvolution workload: sphere fields blurred by a 5^3 Gaussian PSF
+# (sigma 1.5) and corrupted by Poisson noise.  Sphere count scales with the
+# volume (320 spheres per 512^3, radii 4-16 px).
+# ----------------------------------------------------------------------------
+
+DECONV_PSF_SIGMA = 1.5
+DECONV_PSF_SIZE = 5
+
+
+def deconv_config(edge: int, seed: int, r_max: float = 16.0) -> SphereConfig:
+    n_spheres = max(2, int(round(320 * (edge / 512.0) ** 3)))
+    return SphereConfig((edge, edge, edge), n_spheres, 4.0, r_max, 2, seed, psf_sigma=DECONV_PSF_SIGMA,
+                        psf_size=DECONV_PSF_SIZE)
+
+
+def deconv_psf() -> np.ndarray:
+    return gaussian_stencil(DECONV_PSF_SIZE, DECONV_PSF_SIGMA)
+
+
+def _deconv_job(args):
+    edge, seed = args
+    a = sphere_apr(deconv_config(edge, seed))
+    return a
+
+
+def deconv_set(edges: Sequence[int], seed0: int, workers: int = 1):
+    """APRs of the deconvolution workload with seeds seed0, seed0 + 1, ...;
+    generated in ``workers`` processes."""
+    jobs = [(int(e), seed0 + i) for i, e in enumerate(edges)]
+    if workers <= 1 or len(jobs) <= 1:
+        return [_deconv_job(j) for j in jobs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=min(workers, len(jobs)), mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_deconv_job, jobs))

@@ -85,6 +85,76 @@ def cpu_baseline(inp, sample: int):
                        f"all {la.n} particles; estimated step {step:.1f} s")}
 
 
+SURROGATE_EVAL = {
+    # 8 APRs of uneven sizes; "full" is the 256^3-768^3 batch (about 6 CPU
+    # minutes to generate), "small" the default
+    "small": (160, 192, 224, 256, 288, 320, 352, 384),
+    "full": (256, 320, 384, 448, 512, 576, 640, 768),
+}
+SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2112_03592_amd", "weights", "rl10_surrogate.npz")
+
+
+def surrogate_inputs(which: str):
+    """The batch's APRs, generated in worker processes (before this process
+    touches the GPU)."""
+    from aprgen.apr_input import deconv_set
+    t0 = time.perf_counter()
+    inputs = deconv_set(SURROGATE_EVAL[which], 7000, workers=8)
+    log(f"surrogate batch {SURROGATE_EVAL[which]} generated in {time.perf_counter() - t0:.1f} s")
+    return inputs
+
+
+def surrogate_leg(which: str, inputs, reps: int = 3):
+    """Plain 10-iteration APR Richardson-Lucy against the surrogate (start
+    iterations + network + monitor, plus the plain iteration when the monitor
+    rejects) on a batch of deconvolution APRs; relative L2 error of the
+    returned values against the plain result (FP32 on the device)."""
+    import numpy as np
+    import torch
+    from paper_2112_03592_amd import apr as G
+    from paper_2112_03592_amd import surrogate as N
+    edges = SURROGATE_EVAL[which]
+    sur = N.load_surrogate(SURROGATE_WEIGHTS)
+    ws = G.Workspace(16)
+    rec = {"edges": list(edges), "n_particles": [], "plain_ms": [], "surrogate_ms": [], "error": [],
+           "monitor": [], "fallback": []}
+    for inp in inputs:
+        acc = G.AprAccess.from_input(inp, gather=(3,))
+        u = torch.from_numpy(np.maximum(inp.values, 0).astype(np.float32)).cuda()
+        t = sur.plain(acc, u)
+        res = sur(acc, u)                      # warm-up of both paths
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            sur.plain(acc, u)
+        b.record()
+        torch.cuda.synchronize()
+        plain_ms = a.elapsed_time(b) / reps
+        w0 = time.perf_counter()
+        for _ in range(reps):
+            res = sur(acc, u)                  # includes the monitor's host synchronisation
+        torch.cuda.synchronize()
+        sur_ms = (time.perf_counter() - w0) * 1e3 / reps
+        rec["n_particles"].append(inp.n_particles)
+        rec["plain_ms"].append(plain_ms)
+        rec["surrogate_ms"].append(sur_ms)
+        rec["error"].append(N.rel_error(res.values, t, ws))
+        rec["monitor"].append(res.monitor)
+        rec["fallback"].append(bool(res.fallback))
+        log(f"  {inp.dims[0]}^3 N_p={inp.n_particles}: plain {plain_ms:.3f} ms, surrogate {sur_ms:.3f} ms, "
+            f"error {rec['error'][-1]:.4f}, monitor {res.monitor:.4f}, fallback {res.fallback}")
+        sur.rl.forget(acc)
+        acc.close()
+        del t, res, u
+    rec["speedup"] = float(np.sum(rec["plain_ms"]) / np.sum(rec["surrogate_ms"]))
+    rec["max_error"] = float(np.max(rec["error"]))
+    rec["tau"] = sur.tau
+    rec["start"] = {"iterations": sur.n_pre, "power": sur.power}
+    rec["batch"] = which
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +163,8 @@ def main():
     ap.add_argument("--workload", default="sphere512")
     ap.add_argument("--cpu-sample", type=int, default=1 << 15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--surrogate-eval", default="small", choices=["small", "full", "none"],
+                    help="batch of the surrogate-vs-plain Richardson-Lucy comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -115,6 +187,10 @@ def main():
     import torch
     from aprgen.apr_input import CONFIGS, cached_sphere_apr
     from paper_2112_03592_amd import apr as G
+
+    sur_inputs = None
+    if args.surrogate_eval != "none" and os.path.exists(SURROGATE_WEIGHTS):
+        sur_inputs = surrogate_inputs(args.surrogate_eval)
 
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
@@ -223,6 +299,11 @@ def main():
         "roofline": roof,
         "source_sha": {k: source_hash(k) for k in KERNEL_SOURCES},
     }
+    if sur_inputs is not None:
+        log(f"surrogate leg ({args.surrogate_eval} batch)")
+        out["surrogate"] = surrogate_leg(args.surrogate_eval, sur_inputs)
+    elif args.surrogate_eval != "none":
+        out["surrogate"] = {"skipped": "no trained weights (python -m paper_2112_03592_amd.train_surrogate)"}
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_sample}-particle sample")
         out["cpu_baseline"] = cpu_baseline(inp, args.cpu_sample)

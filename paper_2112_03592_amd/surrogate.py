@@ -344,3 +344,20 @@ def calibrate_tau(monitors: Sequence[float], errors: Sequence[float], target: fl
             break
         tau = float(v)
     return tau
+
+
+def save_surrogate(path: str, sur: RLSurrogate, **extra) -> None:
+    """Weights, network configuration, start iteration (n_pre, power), tau and
+    any extra arrays (training record) in one .npz file."""
+    d = sur.net.state_dict()
+    d.update({"n_iter": np.array(sur.n_iter), "n_pre": np.array(sur.n_pre), "power": np.array(sur.power),
+              "tau": np.array(sur.tau), "psf": np.asarray(sur.rl.psf)})
+    d.update({k: np.asarray(v) for k, v in extra.items()})
+    np.savez(path, **d)
+
+
+def load_surrogate(path: str, device="cuda", act_dtype: torch.dtype = torch.bfloat16) -> RLSurrogate:
+    net = SurrogateNet.load(path, device=device)
+    with np.load(path, allow_pickle=False) as f:
+        return RLSurrogate(net, f["psf"], int(f["n_iter"]), int(f["n_pre"]), float(f["power"]), float(f["tau"]),
+                           act_dtype=act_dtype)

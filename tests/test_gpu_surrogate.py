@@ -1,13 +1,15 @@
 """GPU parity of the surrogate-network entry points and of the network's
 forward and gradient against the FP64 oracle; the autograd wrapper; the
 over-relaxed Richardson-Lucy start; training gain; monitor and fallback."""
+import os
 import sys
 
 import numpy as np
 import pytest
 import torch
 
-from aprgen.apr_input import CONFIGS, SphereConfig, gaussian_stencil, random_apr, sphere_apr
+from aprgen.apr_input import (CONFIGS, SphereConfig, deconv_config, deconv_psf, deconv_set, gaussian_stencil,
+                              random_apr, sphere_apr)
 from oracle import access as A
 from oracle import conv as C
 from oracle import surrogate as S
@@ -245,3 +247,60 @@ def test_calibrate_tau_rule():
     assert N.calibrate_tau([0.1, 0.2], [0.03, 0.01], 0.02) == 0.0
     assert N.calibrate_tau([0.2, 0.2, 0.1], [0.01, 0.03, 0.01], 0.02) == 0.1
     assert N.calibrate_tau([0.1, 0.3], [0.01, 0.01], 0.02) == 0.3
+
+
+# ---------------------------------------------------------------------------
+# the trained surrogate (weights written by train_surrogate on the GPU)
+# ---------------------------------------------------------------------------
+
+TRAINED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2112_03592_amd",
+                       "weights", "rl10_surrogate.npz")
+
+
+@pytest.mark.parametrize("edge,seed", [(96, 8001), (112, 8003), (128, 8002)])
+def test_trained_surrogate_against_fp64_oracle_rl10(edge, seed):
+    """Held-out deconvolution APR: the trained surrogate is accepted by its
+    monitor and lies within 2e-2 of the FP64 oracle's 10 Richardson-Lucy
+    iterations; it gains over its start (the over-relaxed iterations alone),
+    over the same network untrained, and over the input."""
+    say("trained", edge, seed)
+    inp = sphere_apr(deconv_config(edge, seed))
+    la = linear_access(inp)
+    psf = deconv_psf()
+    u = np.maximum(inp.values, 0).astype(np.float32)
+    t = oracle_rl(la, u.astype(np.float64), psf, 10)
+    sur = N.load_surrogate(TRAINED)
+    fresh = N.RLSurrogate(N.SurrogateNet(N.NetConfig(seed=7)), psf, 10, sur.n_pre, sur.power)
+    with G.AprAccess.from_input(inp, gather=(3,)) as acc:
+        ud = dev(u)
+        res = sur(acc, ud)
+        s = res.values.cpu().numpy().astype(np.float64)
+        base = sur.base(acc, ud).cpu().numpy().astype(np.float64)
+        s_fresh = fresh.estimate(acc, ud)[0].cpu().numpy().astype(np.float64)
+        plain = sur.plain(acc, ud).cpu().numpy().astype(np.float64)
+
+    def err(a):
+        return float(np.linalg.norm(a - t) / np.linalg.norm(t))
+
+    say(f"  error: surrogate {err(s):.4f} start {err(base):.4f} untrained {err(s_fresh):.4f} "
+        f"input {err(u):.4f} plain FP32 {err(plain):.2e}; monitor {res.monitor:.4f} tau {sur.tau:.4f}")
+    assert err(plain) < 1e-4
+    assert not res.fallback
+    assert err(s) <= 2e-2
+    assert err(s) < 0.75 * err(base)
+    assert err(s) < 0.75 * err(s_fresh)
+    assert err(s) < 0.1 * err(u)
+
+
+def test_short_training_reduces_the_loss():
+    rl = N.RichardsonLucy(deconv_psf())
+    cases = []
+    for inp in deconv_set((64, 80), 8100):
+        acc = G.AprAccess.from_input(inp, gather=(3,))
+        u = dev(np.maximum(inp.values, 0))
+        cases.append((acc, rl(acc, u, 4, power=2.0), rl(acc, u, 10)))
+    net = N.SurrogateNet(N.NetConfig(seed=11))
+    losses = N.train(net, cases, 80, lr=2e-3, log_every=1)
+    for acc, _, _ in cases:
+        acc.close()
+    assert np.mean(losses[-10:]) < 0.7 * np.mean(losses[:2]), (losses[:2], losses[-10:])
