@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--surrogate-eval", default="small", choices=["small", "full", "none"],
                     help="batch of the surrogate-vs-plain Richardson-Lucy comparison")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="run only the surrogate comparison and print its record (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -195,6 +197,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.surrogate_only:
+        print(json.dumps(surrogate_leg(args.surrogate_eval, sur_inputs) if sur_inputs is not None
+                         else {"skipped": "no trained weights or --surrogate-eval none"}), flush=True)
+        return
     log(f"workload {args.workload}: generating / loading input")
     inp = cached_sphere_apr(args.workload)
     cfg = CONFIGS[args.workload]

@@ -595,8 +595,8 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
     APR_TRY(dev_alloc(h, &h->gmap[gi], h->n_p * int64_t(k * k * k)));
     APR_TRY(build_gather_map(h, k, h->gmap[gi], s));
   }
-  // ---- child map of the tree nodes (fill of many channels)
-  if ((h->gmap[0] || h->gmap[1]) && h->n_t > 0) {
+  // ---- child map of the tree nodes (tree fills); codes hold 31-bit indices
+  if (h->n_t > 0 && h->n_p < (int64_t(1) << 31) - 1) {
     APR_TRY(dev_alloc(h, &h->cmap, h->n_t * 8));
     APR_TRY(build_child_map(h, h->cmap, s));
   }

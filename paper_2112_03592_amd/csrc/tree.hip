@@ -5,10 +5,12 @@
 // scattered into an LDS slot array, then each lane sums the children of one
 // parent in a fixed order (deterministic, no atomics).
 //
-// Many channels: the same kernel run once in index mode writes every node's
-// child list (child map, [8][N_t], fixed child order); the fill of all
-// channels is then a gather over that map, one lane per node, with the same
-// summation order as the one-channel kernel.
+// The same kernel run once in index mode (at access build) writes every
+// node's child list (child map, [8][N_t], fixed child order); fills are then
+// gathers over that map, one lane per node, with the same summation order as
+// the row-window kernel (which remains the path of handles without a child
+// map).  The coarse levels, which hold few nodes, are filled by one
+// workgroup in a single launch.
 #include "common.hpp"
 
 namespace apr {
@@ -122,34 +124,78 @@ __global__ __launch_bounds__(64 * kFillWaves) void fill_level_kernel(
   }
 }
 
-// Mean of the children of every tree node of one level over CH channels,
-// one lane per node, children in child-map order (the order of the
-// one-channel kernel: bit-identical results).
+// Mean of the children of tree node i over the channels (CH > 0: CH
+// channels, vector row access; CH == 0: C channels, scalar loop), children
+// in child-map order -- the order of the one-channel kernel, so results are
+// bit-identical to it.
 template <typename T, int CH>
-__global__ __launch_bounds__(256) void fill_mc_kernel(const uint32_t* __restrict__ cmap, int64_t n_t,
-                                                      uint32_t t_begin, uint32_t t_end, const T* __restrict__ x,
-                                                      T* __restrict__ tree) {
-  const uint32_t i = t_begin + blockIdx.x * 256u + threadIdx.x;
-  if (i >= t_end) return;
-  float s[CH];
+__device__ inline void fill_node(const uint32_t* __restrict__ cmap, int64_t n_t, uint32_t i,
+                                 const T* __restrict__ x, T* __restrict__ tree, int C) {
+  uint32_t code[8];
 #pragma unroll
-  for (int c = 0; c < CH; ++c) s[c] = 0.f;
-  int n = 0;
+  for (int j = 0; j < 8; ++j) code[j] = cmap[size_t(j) * n_t + i];
+  if constexpr (CH > 0) {
+    float s[CH];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const uint32_t code = cmap[size_t(j) * n_t + i];
-    if (code == kChildPad) continue;
-    const T* src = ((code >> 31) ? tree : x) + size_t(code & 0x7fffffffu) * CH;
-    float v[CH];
-    load_vec<T, CH>(src, v);
+    for (int c = 0; c < CH; ++c) s[c] = 0.f;
+    int n = 0;
 #pragma unroll
-    for (int c = 0; c < CH; ++c) s[c] += v[c];
-    ++n;
+    for (int j = 0; j < 8; ++j) {
+      if (code[j] == kChildPad) continue;
+      float v[CH];
+      load_vec<T, CH>(((code[j] >> 31) ? tree : x) + size_t(code[j] & 0x7fffffffu) * CH, v);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) s[c] += v[c];
+      ++n;
+    }
+    T out[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) out[c] = from_f32<T>(s[c] / float(n));
+    store_vec<T, CH>(tree + size_t(i) * CH, out);
+  } else {
+    for (int c = 0; c < C; ++c) {
+      float s = 0.f;
+      int n = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (code[j] == kChildPad) continue;
+        s += to_f32<T>((((code[j] >> 31) ? tree : x) + size_t(code[j] & 0x7fffffffu) * C)[c]);
+        ++n;
+      }
+      tree[size_t(i) * C + c] = from_f32<T>(s / float(n));
+    }
   }
-  T out[CH];
-#pragma unroll
-  for (int c = 0; c < CH; ++c) out[c] = from_f32<T>(s[c] / float(n));
-  store_vec<T, CH>(tree + size_t(i) * CH, out);
+}
+
+constexpr int kFillFlat = 256;
+constexpr int kFillSmallThreads = 1024;
+constexpr int64_t kFillSmall = 16384;   // coarse levels up to this many nodes in all go to one workgroup
+
+// one tree level, one lane per node
+template <typename T, int CH>
+__global__ __launch_bounds__(kFillFlat) void fill_flat_kernel(const uint32_t* __restrict__ cmap, int64_t n_t,
+                                                              uint32_t t_begin, uint32_t t_end,
+                                                              const T* __restrict__ x, T* __restrict__ tree, int C) {
+  const uint32_t i = t_begin + blockIdx.x * uint32_t(kFillFlat) + threadIdx.x;
+  if (i < t_end) fill_node<T, CH>(cmap, n_t, i, x, tree, C);
+}
+
+struct LevelSpans {
+  uint32_t begin[kMaxL + 1];   // first tree node of level L (nodes of L: [begin[L], begin[L + 1]))
+};
+
+// the coarse levels [L_lo, L_hi], finest first, by one workgroup (a barrier
+// between levels orders each level after its children)
+template <typename T, int CH>
+__global__ __launch_bounds__(kFillSmallThreads) void fill_small_kernel(const uint32_t* __restrict__ cmap, int64_t n_t,
+                                                                        LevelSpans sp, int L_lo, int L_hi,
+                                                                        const T* __restrict__ x,
+                                                                        T* __restrict__ tree, int C) {
+  for (int L = L_hi; L >= L_lo; --L) {
+    for (uint32_t i = sp.begin[L] + threadIdx.x; i < sp.begin[L + 1]; i += kFillSmallThreads)
+      fill_node<T, CH>(cmap, n_t, i, x, tree, C);
+    __syncthreads();
+  }
 }
 
 }  // namespace apr
@@ -170,22 +216,43 @@ apr_status build_child_map(const apr_handle* h, uint32_t* cmap, hipStream_t s) {
 }
 
 template <typename T, int CH>
-static apr_status fill_mc(const apr_handle* h, const T* x, T* tree, hipStream_t s) {
+static apr_status fill_by_child_map(const apr_handle* h, const T* x, T* tree, int C, hipStream_t s) {
   const Meta& m = h->meta;
-  uint32_t lvl_begin[kMaxL + 1];
+  LevelSpans sp{};
   uint32_t acc = 0;
   for (int L = m.t_lo; L <= m.t_hi; ++L) {
-    lvl_begin[L] = acc;
+    sp.begin[L] = acc;
     acc += uint32_t(h->per_level_t[L]);
   }
-  for (int L = m.t_hi; L >= m.t_lo; --L) {
-    const uint32_t b = lvl_begin[L], e = b + uint32_t(h->per_level_t[L]);
-    if (b == e) continue;
-    hipLaunchKernelGGL((fill_mc_kernel<T, CH>), dim3((e - b + 255) / 256), dim3(256), 0, s, h->cmap, h->n_t, b, e,
-                       x, tree);
-    APR_HIP(hipGetLastError());
+  sp.begin[m.t_hi + 1] = acc;
+  // coarse levels whose nodes together fit one workgroup's sweep
+  int L_small = m.t_lo - 1;
+  int64_t small = 0;
+  while (L_small + 1 <= m.t_hi && small + h->per_level_t[L_small + 1] <= kFillSmall) {
+    ++L_small;
+    small += h->per_level_t[L_small];
   }
+  for (int L = m.t_hi; L > L_small; --L) {
+    const uint32_t b = sp.begin[L], e = sp.begin[L + 1];
+    if (b == e) continue;
+    hipLaunchKernelGGL((fill_flat_kernel<T, CH>), dim3((e - b + kFillFlat - 1) / kFillFlat), dim3(kFillFlat), 0, s,
+                       h->cmap, h->n_t, b, e, x, tree, C);
+  }
+  if (L_small >= m.t_lo && small > 0)
+    hipLaunchKernelGGL((fill_small_kernel<T, CH>), dim3(1), dim3(kFillSmallThreads), 0, s, h->cmap, h->n_t, sp,
+                       m.t_lo, L_small, x, tree, C);
+  APR_HIP(hipGetLastError());
   return APR_OK;
+}
+
+template <typename T>
+static apr_status fill_dispatch(const apr_handle* h, const void* xv, void* tv, int C, hipStream_t s) {
+  const T* x = static_cast<const T*>(xv);
+  T* tree = static_cast<T*>(tv);
+  const bool aligned16 = ((reinterpret_cast<uintptr_t>(xv) | reinterpret_cast<uintptr_t>(tv)) & 15) == 0;
+  if (C == 1) return fill_by_child_map<T, 1>(h, x, tree, 1, s);
+  if (C == 16 && aligned16) return fill_by_child_map<T, 16>(h, x, tree, 16, s);
+  return fill_by_child_map<T, 0>(h, x, tree, C, s);
 }
 }  // namespace apr
 
@@ -197,12 +264,10 @@ extern "C" apr_status apr_fill_tree(const apr_handle* h, const void* x, void* tr
   if (h->n_t == 0) return APR_OK;
   if (!x || !tree) APR_FAIL(APR_EINVAL, "apr_fill_tree: null x or tree");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (channels == 16 && h->cmap && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 15) == 0) {
-    if (dtype == APR_F32)
-      return fill_mc<float, 16>(h, static_cast<const float*>(x), static_cast<float*>(tree), s);
-    return fill_mc<__hip_bfloat16, 16>(h, static_cast<const __hip_bfloat16*>(x), static_cast<__hip_bfloat16*>(tree),
-                                       s);
-  }
+  if (h->cmap)
+    return dtype == APR_F32 ? fill_dispatch<float>(h, x, tree, channels, s)
+                            : fill_dispatch<__hip_bfloat16>(h, x, tree, channels, s);
+  // without a child map (more than 2^31 - 1 particles): the row-window kernel
   const Meta& m = h->meta;
   for (int L = m.t_hi; L >= m.t_lo; --L) {
     const int64_t rows = int64_t(m.dz[L]) * m.dx[L];
