@@ -55,6 +55,16 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup barrier that orders LDS only: global loads and stores still in
+// flight stay in flight (a plain __syncthreads() also waits for every
+// outstanding store).  For kernels whose threads exchange data through LDS
+// alone and never read global memory written by another thread.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ inline void row_range(const uint32_t* __restrict__ ends, uint32_t row, uint32_t& b,
                                  uint32_t& e) {
   e = ends[row];

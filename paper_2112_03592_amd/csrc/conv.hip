@@ -2,8 +2,8 @@
 // re-shaped for wave64 / CDNA4.
 //
 // Work item: one tile of kTileZ x kTileX particle rows (z, x) at one level l,
-// from the non-empty tile list (the pre-pass of Section 5.2).  A workgroup of
-// 512 threads sweeps its tile along y in chunks; each chunk starts at the
+// from the non-empty tile list (the pre-pass of Section 5.2).  A workgroup
+// (512 threads for 3^3, 1024 for 5^3) sweeps its tile along y in chunks; each chunk starts at the
 // smallest unprocessed y of the tile's output particles (empty stretches are
 // skipped) and spans at most kYC cells.  Per chunk:
 //   B. list the output particles of the centre rows that fall in
@@ -18,7 +18,8 @@
 //   D. every listed particle accumulates its k^3 taps from the patch in FP32
 //      (weights in scalar registers) and writes its output.
 // Per-row bookkeeping uses one writer per row (the last element of a prefix),
-// no atomics.  The blockIdx -> tile map gives each XCD a contiguous run of
+// no atomics.  Threads share data through LDS only (outputs are never read
+// back), so the barriers order LDS and leave stores in flight.  The blockIdx -> tile map gives each XCD a contiguous run of
 // tiles so that halo rows shared by neighbouring tiles hit the same L2.
 #include <type_traits>
 
@@ -28,9 +29,18 @@ namespace apr {
 
 constexpr int kYC = 64;          // output cells per chunk along y
 constexpr int kBig = 1 << 28;    // y of an element past the end of its row
-constexpr int kBatch = 4;        // independent elements per thread in flight
 constexpr int kRowIdCap = 3584;  // patch items per chunk with a stored source row
-constexpr int kConvThreads = 512;
+// Launch shape per stencil size.  The kernel waits on memory most of the
+// time, so resident waves decide its speed: the 3^3 patch lets three
+// workgroups share a CU once registers are capped for six waves per SIMD;
+// the larger 5^3 patch allows two, so those workgroups are 1024 threads wide
+// (eight waves per SIMD) with fewer elements in flight per thread.
+template <int K>
+struct ConvShape {
+  static constexpr int kThreads = K == 3 ? 512 : 1024;
+  static constexpr int kBatch = K == 3 ? 4 : 2;        // independent elements per thread in flight
+  static constexpr int kWavesPerSimd = K == 3 ? 6 : 8;
+};
 
 struct ConvArgs {
   Meta m;
@@ -97,8 +107,10 @@ __device__ inline int find_row(const uint32_t* pre, int n, uint32_t v) {
 }
 
 template <int K, typename TX, typename TY, bool INDEX>
-__global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
-  constexpr int NT = kConvThreads, NW = NT / 64;
+__global__ __launch_bounds__(ConvShape<K>::kThreads)
+__attribute__((amdgpu_waves_per_eu(ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
+  constexpr int NT = ConvShape<K>::kThreads, NW = NT / 64;
+  constexpr int kBatch = ConvShape<K>::kBatch;
   constexpr int R = K / 2;
   constexpr int TZ = kTileZ, TX_ = kTileX;
   constexpr int HZ = TZ + 2 * R, HX = TX_ + 2 * R;
@@ -204,7 +216,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
     rymax[c] = -1;
     rnext[c] = int(kNoY);
   }
-  __syncthreads();
+  lds_barrier();
   if (wave == 0) {
     int yf0 = int(kNoY);
     if (lane < uint32_t(NC) && op[lane] < oe[lane]) yf0 = int(py[op[lane]]);
@@ -217,7 +229,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
       for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   int par = 0;
   while (true) {
@@ -264,7 +276,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
       }
     }
     if (tid < NSRC) yfirst[tid] = yf;
-    __syncthreads();
+    lds_barrier();
     // every wave reduces the per-row results itself (no extra barrier)
     int ymax_c = (lane < uint32_t(NC)) ? rymax[lane] : -1;
     int ynx = (lane < uint32_t(NC)) ? rnext[lane] : int(kNoY);
@@ -301,7 +313,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
         if (yy < 0 || yy >= Dy) patch[h * PY + p] = pad;
       }
     }
-    __syncthreads();
+    lds_barrier();
     // source row of every patch item (items past kRowIdCap search instead);
     // centre row of every next-chunk listing item
     for (int r = wave; r < NSRC; r += NW) {
@@ -315,7 +327,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
         for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- C (one memory round): reconstruct the level-l patch over [wlo, whi]
     const uint32_t ns = spre[NSRC];
@@ -393,7 +405,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
         if (lo + 1 < drop && !(2 * yn[u] + 1 < drop)) scons[s] = jj[u] + 1;
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- D: accumulate the taps of every listed particle
     for (int s = tid; s < NSRC; s += NT) {
@@ -461,7 +473,7 @@ __global__ __launch_bounds__(kConvThreads) void conv1_kernel(ConvArgs a) {
         yo[idx] = from_f32<TY>(acc);
       }
     }
-    __syncthreads();
+    lds_barrier();
     par ^= 1;
   }
 }
@@ -471,12 +483,12 @@ static apr_status launch_conv(const ConvArgs& args, int xdt, int ydt, hipStream_
   const int64_t per = (args.n_tiles + 7) / 8;
   const dim3 grid(unsigned(per * 8));
   if (xdt == APR_F32 && ydt == APR_F32)
-    hipLaunchKernelGGL((conv1_kernel<K, float, float, INDEX>), grid, dim3(kConvThreads), 0, s, args);
+    hipLaunchKernelGGL((conv1_kernel<K, float, float, INDEX>), grid, dim3(ConvShape<K>::kThreads), 0, s, args);
   else if (xdt == APR_BF16 && ydt == APR_BF16)
-    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, __hip_bfloat16, INDEX>), grid, dim3(kConvThreads), 0,
+    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, __hip_bfloat16, INDEX>), grid, dim3(ConvShape<K>::kThreads), 0,
                        s, args);
   else if (xdt == APR_BF16 && ydt == APR_F32)
-    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, float, INDEX>), grid, dim3(kConvThreads), 0, s, args);
+    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, float, INDEX>), grid, dim3(ConvShape<K>::kThreads), 0, s, args);
   else
     APR_FAIL(APR_EUNSUPPORTED, "apr_conv: unsupported dtype combination");
   APR_HIP(hipGetLastError());
