@@ -281,32 +281,37 @@ __device__ inline void tile_locate(const TileLevels& tl, int64_t t, int& l, int&
   tx = int(r % tl.ntx[j]);
 }
 
+// flags[t] = tile t holds particles; ymin[t] = smallest y among them
 __global__ void tile_flag_kernel(Meta m, TileLevels tl, const uint32_t* __restrict__ pend,
-                                 uint32_t* flags, int64_t n) {
+                                 const uint16_t* __restrict__ py, uint32_t* flags, uint32_t* ymin, int64_t n) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n) return;
   int l, tz, tx;
   tile_locate(tl, t, l, tz, tx);
-  uint32_t any = 0;
+  uint32_t any = 0, y0 = 0xffffu;
   for (int a = 0; a < kTileZ; ++a)
     for (int b = 0; b < kTileX; ++b) {
       const int z = tz * kTileZ + a, x = tx * kTileX + b;
       if (z >= m.dz[l] || x >= m.dx[l]) continue;
       uint32_t rb, re;
       row_range(pend, m.prow[l] + uint32_t(z) * m.dx[l] + x, rb, re);
-      any |= (re > rb);
+      if (re > rb) {
+        any = 1;
+        y0 = min(y0, uint32_t(py[rb]));
+      }
     }
   flags[t] = any;
+  ymin[t] = y0;
 }
 
 __global__ void tile_compact_kernel(TileLevels tl, const uint32_t* __restrict__ flags_scanned,
-                                    const uint32_t* __restrict__ flags_raw, uint64_t* out,
-                                    int64_t n) {
+                                    const uint32_t* __restrict__ flags_raw, const uint32_t* __restrict__ ymin,
+                                    uint64_t* out, int64_t n) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n || !flags_raw[t]) return;
   int l, tz, tx;
   tile_locate(tl, t, l, tz, tx);
-  out[flags_scanned[t]] = tile_pack(l, tz, tx);
+  out[flags_scanned[t]] = tile_pack(l, tz, tx, int(ymin[t]));
 }
 
 // ---------------------------------------------------------------------------
@@ -568,8 +573,12 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
     APR_TRY_HIP(hipMalloc(&q2, size_t(ntot + 1) * 4));
     tmp.push_back(q2);
     uint32_t* sc = static_cast<uint32_t*>(q2);
+    void* q3 = nullptr;
+    APR_TRY_HIP(hipMalloc(&q3, size_t(ntot + 1) * 4));
+    tmp.push_back(q3);
+    uint32_t* ymin = static_cast<uint32_t*>(q3);
     hipLaunchKernelGGL(tile_flag_kernel, dim3(unsigned((ntot + 255) / 256)), dim3(256), 0, s, m,
-                       tl, h->pend, raw, ntot);
+                       tl, h->pend, h->py, raw, ymin, ntot);
     APR_TRY_HIP(hipGetLastError());
     APR_TRY_HIP(hipMemcpyAsync(sc, raw, size_t(ntot) * 4, hipMemcpyDeviceToDevice, s));
     APR_TRY(scan_u32(sc, ntot, d_total, s));
@@ -579,7 +588,7 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
     h->n_tiles = nkeep;
     APR_TRY(dev_alloc(h, &h->tiles, std::max<int64_t>(nkeep, 1)));
     hipLaunchKernelGGL(tile_compact_kernel, dim3(unsigned((ntot + 255) / 256)), dim3(256), 0, s,
-                       tl, sc, raw, h->tiles, ntot);
+                       tl, sc, raw, ymin, h->tiles, ntot);
     APR_TRY_HIP(hipGetLastError());
   }
   // ---- gather maps (multichannel convolution and the backward passes)

@@ -24,13 +24,17 @@ struct Meta {
 };
 
 // Tile descriptor of the convolution work list: level, tile z, tile x.
-__host__ __device__ inline uint64_t tile_pack(int l, int tz, int tx) {
-  return (uint64_t(l) << 48) | (uint64_t(uint32_t(tz)) << 24) | uint64_t(uint32_t(tx));
+// tile list entry: level (8 bits) | first y of the tile's particles (16) |
+// tile z (20) | tile x (20)
+__host__ __device__ inline uint64_t tile_pack(int l, int tz, int tx, int y0) {
+  return (uint64_t(l) << 56) | (uint64_t(uint32_t(y0) & 0xffffu) << 40) | (uint64_t(uint32_t(tz)) << 20) |
+         uint64_t(uint32_t(tx));
 }
-__host__ __device__ inline void tile_unpack(uint64_t t, int& l, int& tz, int& tx) {
-  l = int(t >> 48);
-  tz = int((t >> 24) & 0xffffffu);
-  tx = int(t & 0xffffffu);
+__host__ __device__ inline void tile_unpack(uint64_t t, int& l, int& tz, int& tx, int& y0) {
+  l = int(t >> 56);
+  y0 = int((t >> 40) & 0xffffu);
+  tz = int((t >> 20) & 0xfffffu);
+  tx = int(t & 0xfffffu);
 }
 
 constexpr int kTileZ = 8;   // output rows per tile along z

@@ -108,7 +108,7 @@ __device__ inline int find_row(const uint32_t* pre, int n, uint32_t v) {
 
 template <int K, typename TX, typename TY, bool INDEX>
 __global__ __launch_bounds__(ConvShape<K>::kThreads)
-__attribute__((amdgpu_waves_per_eu(ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
+__attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
   constexpr int NT = ConvShape<K>::kThreads, NW = NT / 64;
   constexpr int kBatch = ConvShape<K>::kBatch;
   constexpr int R = K / 2;
@@ -151,8 +151,8 @@ __attribute__((amdgpu_waves_per_eu(ConvShape<K>::kWavesPerSimd))) void conv1_ker
   const int64_t per = (a.n_tiles + 7) / 8;
   const int64_t t = int64_t(blockIdx.x % 8) * per + int64_t(blockIdx.x / 8);
   if (t >= a.n_tiles) return;
-  int l, tz, tx;
-  tile_unpack(a.tiles[t], l, tz, tx);
+  int l, tz, tx, ty0;
+  tile_unpack(a.tiles[t], l, tz, tx, ty0);
   // workgroup-uniform: keep them in scalar registers
   l = __builtin_amdgcn_readfirstlane(l);
   tz = __builtin_amdgcn_readfirstlane(tz);
@@ -218,10 +218,7 @@ __attribute__((amdgpu_waves_per_eu(ConvShape<K>::kWavesPerSimd))) void conv1_ker
   }
   lds_barrier();
   if (wave == 0) {
-    int yf0 = int(kNoY);
-    if (lane < uint32_t(NC) && op[lane] < oe[lane]) yf0 = int(py[op[lane]]);
-    for (int o = 32; o > 0; o >>= 1) yf0 = min(yf0, __shfl_xor(yf0, o, 64));
-    if (lane == 0) s_y0 = yf0;
+    if (lane == 0) s_y0 = ty0;   // first y of the tile's particles, from the tile list
     wave_scan_into<1>(opre[0], NC, [&](int c) { return min(oe[c] - op[c], uint32_t(OCAP)); });
     wave_lds_sync();
     for (int c = 0; c < NC; ++c) {
