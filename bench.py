@@ -94,6 +94,86 @@ SURROGATE_EVAL = {
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2112_03592_amd", "weights", "rl10_surrogate.npz")
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix peak
+
+
+def layers_leg(inp, reps: int = 10):
+    """The gather path on the same APR: the network layer shapes (1->16,
+    16->16 on MFMA with BF16 activations, 16->16 FP32, 16->1), the 16-channel
+    tree fill, and both gradients of a 16->16 layer (FP32); plus BF16 storage
+    of the single-channel 3^3 / 5^3 convolution against FP32."""
+    import numpy as np
+    import torch
+    from aprgen.apr_input import gaussian_stencil
+    from paper_2112_03592_amd import apr as G
+    n_p = inp.n_particles
+    acc = G.AprAccess.from_input(inp, gather=(3,))
+    nl = acc.n_levels
+    g = torch.Generator(device="cuda").manual_seed(0)
+
+    def rnd(*shape, dtype=torch.float32):
+        return torch.randn(*shape, generator=g, device="cuda").to(dtype)
+
+    def tm(f):
+        f()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    w11 = rnd(nl, 16, 1, 3, 3, 3) * 0.2
+    w1616 = rnd(nl, 16, 16, 3, 3, 3) * 0.05
+    w161 = rnd(nl, 1, 16, 3, 3, 3) * 0.05
+    bias16, bias1 = rnd(16), rnd(1)
+    x1 = torch.from_numpy(inp.values).cuda().view(-1, 1)
+    t1 = G.fill_tree(acc, x1)
+    h16 = rnd(n_p, 16)
+    h16b = h16.to(torch.bfloat16)
+    t16 = G.fill_tree(acc, h16)
+    t16b = G.fill_tree(acc, h16b)
+    dy = rnd(n_p, 16)
+    rec = {"n_particles": n_p, "ms": {}}
+    ms = rec["ms"]
+    ms["fill16_bf16"] = tm(lambda: G.fill_tree(acc, h16b, t16b))
+    ms["fill16_f32"] = tm(lambda: G.fill_tree(acc, h16, t16))
+    ms["fwd_1to16_f32_to_bf16"] = tm(lambda: G.conv(acc, x1, t1, w11, 3, bias=bias16, relu=True,
+                                                     out_dtype=torch.bfloat16))
+    ms["fwd_16to16_bf16_mfma"] = tm(lambda: G.conv(acc, h16b, t16b, w1616, 3, bias=bias16, relu=True))
+    ms["fwd_16to16_f32"] = tm(lambda: G.conv(acc, h16, t16, w1616, 3, bias=bias16, relu=True))
+    ms["fwd_16to1_bf16_to_f32"] = tm(lambda: G.conv(acc, h16b, t16b, w161, 3, bias=bias1,
+                                                     out_dtype=torch.float32))
+    ms["bwd_data_16to16_f32"] = tm(lambda: G.conv_bwd_data(acc, dy, w1616, 3))
+    ms["bwd_weight_16to16_f32"] = tm(lambda: G.conv_bwd_weight(acc, h16, t16, dy, 3, nl, 16, 16))
+    # MFMA layer against the BF16 matrix peak and the HBM roofline: gathered
+    # rows (BF16, 16 channels) of particles and tree, the gather map, outputs
+    t = ms["fwd_16to16_bf16_mfma"] * 1e-3
+    flops = 2.0 * 27 * 16 * 16 * n_p
+    bytes_alg = n_p * 32 + acc.n_tree * 32 + n_p * 27 * 4 + n_p * 32
+    rec["mfma_16to16"] = {"tflops": flops / t / 1e12, "frac_mfma_bf16": flops / t / 1e12 / MFMA_BF16_PEAK_TFLOPS,
+                          "GBps": bytes_alg / t / 1e9, "frac_hbm": bytes_alg / t / 1e9 / HBM_PEAK_GBPS,
+                          "algorithmic_bytes": bytes_alg}
+    # BF16 storage, single channel
+    xs = torch.from_numpy(inp.values).cuda()
+    xb = xs.to(torch.bfloat16)
+    ts, tb = G.fill_tree(acc, xs), G.fill_tree(acc, xb)
+    prec = {}
+    for k in (3, 5):
+        w = torch.from_numpy(G.stencil_levels(gaussian_stencil(k, 1.0), "same", k, inp.l_min, inp.l_max)).cuda()
+        yf = G.conv(acc, xs, ts, w, k)
+        yb = G.conv(acc, xb, tb, w, k, out_dtype=torch.float32)
+        d = (yb.double() - yf.double()).norm() / yf.double().norm()
+        prec[f"conv{k}"] = {"bf16_ms": tm(lambda: G.conv(acc, xb, tb, w, k, out_dtype=torch.float32)),
+                            "f32_ms": tm(lambda: G.conv(acc, xs, ts, w, k, y=yf)),
+                            "bf16_vs_f32_rel_l2": float(d)}
+    rec["bf16_single_channel"] = prec
+    acc.close()
+    return rec
+
+
 def surrogate_inputs(which: str):
     """The batch's APRs, generated in worker processes (before this process
     touches the GPU)."""
@@ -165,6 +245,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--surrogate-eval", default="small", choices=["small", "full", "none"],
                     help="batch of the surrogate-vs-plain Richardson-Lucy comparison")
+    ap.add_argument("--no-layers", action="store_true", help="skip the gather-path layer timings")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate comparison and print its record (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -305,6 +386,9 @@ def main():
         "roofline": roof,
         "source_sha": {k: source_hash(k) for k in KERNEL_SOURCES},
     }
+    if not args.no_layers:
+        log("layers leg (gather path, 16 channels; BF16 storage)")
+        out["layers"] = layers_leg(inp)
     if sur_inputs is not None:
         log(f"surrogate leg ({args.surrogate_eval} batch)")
         out["surrogate"] = surrogate_leg(args.surrogate_eval, sur_inputs)

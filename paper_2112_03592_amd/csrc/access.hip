@@ -319,6 +319,9 @@ __global__ void tile_compact_kernel(TileLevels tl, const uint32_t* __restrict__ 
 // ---------------------------------------------------------------------------
 apr_status build_gather_map(const apr_handle* h, int k, int32_t* map32, hipStream_t s);
 apr_status build_child_map(const apr_handle* h, uint32_t* cmap, hipStream_t s);
+apr_status build_inverse_map(apr_handle* h, int k, hipStream_t s,
+                             apr_status (*alloc_u32)(apr_handle*, uint32_t**, int64_t),
+                             apr_status (*scan)(uint32_t*, int64_t, uint32_t*, hipStream_t), uint32_t* total_dev);
 
 static int finest_level(const int32_t* dims) {
   int32_t mx = std::max(dims[0], std::max(dims[1], dims[2]));
@@ -603,6 +606,7 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
     }
     APR_TRY(dev_alloc(h, &h->gmap[gi], h->n_p * int64_t(k * k * k)));
     APR_TRY(build_gather_map(h, k, h->gmap[gi], s));
+    APR_TRY(build_inverse_map(h, k, s, &dev_alloc<uint32_t>, &scan_u32, d_total));
   }
   // ---- child map of the tree nodes (tree fills); codes hold 31-bit indices
   if (h->n_t > 0 && h->n_p < (int64_t(1) << 31) - 1) {

@@ -159,7 +159,13 @@ struct apr_handle {
   uint64_t* tiles = nullptr;  // conv tiles [n_tiles], finest level first
   int64_t n_tiles = 0;
   int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]
-  uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t] (with the gather maps)
+  uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t]
+  // inverse of the gather maps for the coarse and tree taps: for source s
+  // (particle s as a coarser source, or tree node t at n_p + t) the readers
+  // p * k^3 + q with gmap[q][p] naming s, sorted, at inv_ent[inv_off[s] ..
+  // inv_off[s + 1])
+  uint32_t* inv_off[2] = {nullptr, nullptr};
+  uint32_t* inv_ent[2] = {nullptr, nullptr};
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
 };

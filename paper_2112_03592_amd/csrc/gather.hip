@@ -6,10 +6,10 @@
 //   data grad    the transpose of the forward, evaluated as gathers:
 //                  * same-level readers of a particle s: the particle at
 //                    c_s - o reads s with tap o  (s's own gather map, flipped);
-//                  * finer readers: level-(l+1) particles whose taps land in
-//                    one of the eight children of s (row lookups);
+//                  * finer readers: level-(l+1) particles with s as their
+//                    coarser source, from the inverse of the gather map;
 //                  * tree readers: level-L particles whose taps land on a tree
-//                    node t (row lookups), then the adjoint of the child mean
+//                    node t (inverse map), then the adjoint of the child mean
 //                    pushed from the coarsest tree level down to the particles.
 //   weight grad  dW_l[co, ci, o] = sum_{p at level l} dY[p, co] Xcat[src(p, o), ci],
 //                per-block FP32 sums, FP64 partials, fixed-order FP64 reduce.
@@ -115,127 +115,6 @@ __global__ __launch_bounds__(kFlatThreads) void mc_fwd_kernel(
   store_vec<TY, COUT>(y + size_t(p) * COUT, out);
 }
 
-// ---------------------------------------------------------------------------
-// Data gradient, part 1: for every particle s of level l, the taps of
-// same-level particles (flipped own gather map) and of level-(l+1) particles
-// landing in its children (row lookups).  Writes dx[s] (overwrites).
-// ---------------------------------------------------------------------------
-template <int K, int CIN, int COUT>
-__global__ __launch_bounds__(64 * kGWaves) void bwd_particle_kernel(
-    Meta m, int l, const uint16_t* __restrict__ py, const uint32_t* __restrict__ pend,
-    const int32_t* __restrict__ gmap, int64_t n_p, const float* __restrict__ dy, const float* w_l,
-    const float* w_fine, float* __restrict__ dx) {
-  constexpr int R = K / 2, K3 = K * K * K;
-  const int64_t row = int64_t(blockIdx.x) * kGWaves + threadIdx.x / 64;
-  if (row >= int64_t(m.dz[l]) * m.dx[l]) return;
-  const int z = int(row / m.dx[l]), xr = int(row % m.dx[l]);
-  uint32_t b, e;
-  row_range(pend, m.prow[l] + uint32_t(row), b, e);
-  cfloat* W = as_const(w_l);
-  cfloat* WF = w_fine ? as_const(w_fine) : nullptr;
-  const int lf = l + 1;
-  for (uint32_t s = b + lane_id(); s < e; s += 64) {
-    float acc[CIN];
-#pragma unroll
-    for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
-    // same level: the element at c_s - o is entry (k^3 - 1 - q) of s's map
-#pragma unroll 1
-    for (int q = 0; q < K3; ++q) {
-      const uint32_t g = gmap[size_t(K3 - 1 - q) * size_t(n_p) + s];
-      if (g == kPad || (g >> 30) != 1) continue;
-      const float* gp = dy + size_t(g & kIdxMask) * COUT;
-      float gv[COUT];
-#pragma unroll
-      for (int co = 0; co < COUT; ++co) gv[co] = gp[co];
-#pragma unroll
-      for (int ci = 0; ci < CIN; ++ci)
-#pragma unroll
-        for (int co = 0; co < COUT; ++co) acc[ci] = fmaf(W[(co * CIN + ci) * K3 + q], gv[co], acc[ci]);
-    }
-    // finer level: particles p at 2 c_s + d, d in [-R, 1+R]^3, whose tap
-    // o = b - d lands on child 2 c_s + b (b in {0,1}^3, child in the image)
-    if (WF) {
-      const int ys = py[s];
-      for (int dz = -R; dz <= 1 + R; ++dz)
-        for (int dxo = -R; dxo <= 1 + R; ++dxo) {
-          const int zz = 2 * z + dz, xx = 2 * xr + dxo;
-          if (zz < 0 || xx < 0 || zz >= m.dz[lf] || xx >= m.dx[lf]) continue;
-          uint32_t rb, re;
-          row_range(pend, m.prow[lf] + uint32_t(zz) * m.dx[lf] + xx, rb, re);
-          for (uint32_t i = lower_bound_y(py, rb, re, 2 * ys - R); i < re; ++i) {
-            const int dyo = int(py[i]) - 2 * ys;
-            if (dyo > 1 + R) break;
-            float gv[COUT];
-#pragma unroll
-            for (int co = 0; co < COUT; ++co) gv[co] = dy[size_t(i) * COUT + co];
-            for (int bz = 0; bz < 2; ++bz)
-              for (int bx = 0; bx < 2; ++bx)
-                for (int by = 0; by < 2; ++by) {
-                  if (2 * z + bz >= m.dz[lf] || 2 * xr + bx >= m.dx[lf] || 2 * ys + by >= m.dy[lf]) continue;
-                  const int oz = bz - dz, ox = bx - dxo, oy = by - dyo;
-                  if (oz < -R || oz > R || ox < -R || ox > R || oy < -R || oy > R) continue;
-                  const int q = ((oz + R) * K + (ox + R)) * K + (oy + R);
-#pragma unroll
-                  for (int ci = 0; ci < CIN; ++ci)
-#pragma unroll
-                    for (int co = 0; co < COUT; ++co)
-                      acc[ci] = fmaf(WF[(co * CIN + ci) * K3 + q], gv[co], acc[ci]);
-                }
-          }
-        }
-    }
-#pragma unroll
-    for (int ci = 0; ci < CIN; ++ci) dx[size_t(s) * CIN + ci] = acc[ci];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Data gradient, part 2: tree node t of level L receives the taps of level-L
-// particles landing on it (row lookups).  Writes dt[t] (overwrites; zero for
-// levels without particles).
-// ---------------------------------------------------------------------------
-template <int K, int CIN, int COUT>
-__global__ __launch_bounds__(64 * kGWaves) void bwd_tree_kernel(
-    Meta m, int L, const uint16_t* __restrict__ py, const uint32_t* __restrict__ pend,
-    const uint16_t* __restrict__ ty, const uint32_t* __restrict__ tend, const float* __restrict__ dy,
-    const float* w_L, float* __restrict__ dt) {
-  constexpr int R = K / 2, K3 = K * K * K;
-  const int64_t row = int64_t(blockIdx.x) * kGWaves + threadIdx.x / 64;
-  if (row >= int64_t(m.dz[L]) * m.dx[L]) return;
-  const int z = int(row / m.dx[L]), xr = int(row % m.dx[L]);
-  uint32_t b, e;
-  row_range(tend, m.trow[L] + uint32_t(row), b, e);
-  const bool has_p = L >= m.l_min && L <= m.l_max && w_L;
-  cfloat* W = has_p ? as_const(w_L) : nullptr;
-  for (uint32_t t = b + lane_id(); t < e; t += 64) {
-    float acc[CIN];
-#pragma unroll
-    for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
-    if (has_p) {
-      const int yt = ty[t];
-      for (int oz = -R; oz <= R; ++oz)
-        for (int ox = -R; ox <= R; ++ox) {
-          const int zz = z - oz, xx = xr - ox;   // reader p at c_t - o
-          if (zz < 0 || xx < 0 || zz >= m.dz[L] || xx >= m.dx[L]) continue;
-          uint32_t rb, re;
-          row_range(pend, m.prow[L] + uint32_t(zz) * m.dx[L] + xx, rb, re);
-          for (uint32_t i = lower_bound_y(py, rb, re, yt - R); i < re; ++i) {
-            const int oy = yt - int(py[i]);
-            if (oy < -R) break;
-            const int q = ((oz + R) * K + (ox + R)) * K + (oy + R);
-#pragma unroll
-            for (int ci = 0; ci < CIN; ++ci)
-#pragma unroll
-              for (int co = 0; co < COUT; ++co)
-                acc[ci] = fmaf(W[(co * CIN + ci) * K3 + q], dy[size_t(i) * COUT + co], acc[ci]);
-          }
-        }
-    }
-#pragma unroll
-    for (int ci = 0; ci < CIN; ++ci) dt[size_t(t) * CIN + ci] = acc[ci];
-  }
-}
-
 // number of children of a level-L cell that lie in the image
 __device__ inline int n_children(const Meta& m, int L, int z, int x, int y) {
   const int C = L + 1;
@@ -243,7 +122,7 @@ __device__ inline int n_children(const Meta& m, int L, int z, int x, int y) {
 }
 
 // ---------------------------------------------------------------------------
-// Data gradient, part 3: adjoint of the child mean.  For every element at
+// Data gradient, last step: adjoint of the child mean.  For every element at
 // level L (tree node, or particle when `to_particles`), add its parent's
 // accumulated gradient divided by the parent's child count.  Launched level
 // by level from the coarsest, so the parent's value is final.
@@ -530,24 +409,209 @@ apr_status mc_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, c
                              "(16,16) (16,1) (2,3); k=5 (1,1) (2,3)");
 }
 
+// ---------------------------------------------------------------------------
+// Inverse map of the coarse and tree taps (built once with the gather map):
+// counts per source, exclusive scan, fill, then each source's readers sorted
+// (the fill order of the atomics is arbitrary; the sort makes it fixed).
+// ---------------------------------------------------------------------------
+__device__ inline int64_t inv_target(uint32_t g, int64_t n_p) {
+  const uint32_t t = g >> 30;
+  if (g == kPad || t == 1) return -1;
+  return t == 2 ? int64_t(g & kIdxMask) : n_p + int64_t(g & kIdxMask);
+}
+
+__global__ void inv_count_kernel(const uint32_t* __restrict__ gmap, int64_t n_p, int64_t n_pairs,
+                                 uint32_t* __restrict__ count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_pairs) return;
+  const int64_t t = inv_target(gmap[i], n_p);
+  if (t >= 0) atomicAdd(&count[t], 1u);
+}
+
+__global__ void inv_fill_kernel(const uint32_t* __restrict__ gmap, int64_t n_p, int64_t n_pairs, int k3,
+                                const uint32_t* __restrict__ off, uint32_t* __restrict__ cursor,
+                                uint32_t* __restrict__ ent) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // i = q * n_p + p
+  if (i >= n_pairs) return;
+  const int64_t t = inv_target(gmap[i], n_p);
+  if (t < 0) return;
+  const uint32_t q = uint32_t(i / n_p), p = uint32_t(i % n_p);
+  ent[off[t] + atomicAdd(&cursor[t], 1u)] = p * uint32_t(k3) + q;
+}
+
+__global__ void inv_sort_kernel(const uint32_t* __restrict__ off, int64_t n_targets, uint32_t* __restrict__ ent) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_targets) return;
+  const uint32_t b = off[t], e = off[t + 1];
+  for (uint32_t i = b + 1; i < e; ++i) {
+    const uint32_t v = ent[i];
+    uint32_t j = i;
+    while (j > b && ent[j - 1] > v) {
+      ent[j] = ent[j - 1];
+      --j;
+    }
+    ent[j] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Data gradient on the gather map and its inverse, one lane per element:
+//   particles of level l: same-level readers (own map, flipped taps) with
+//   W_l, then the level-(l+1) readers that use the particle as their coarser
+//   source (inverse map) with W_(l+1); one write per particle;
+//   tree nodes of level L: the level-L readers landing on the node (inverse
+//   map) with W_L.  Weights are staged in LDS as [tap][c_out][c_in].
+// ---------------------------------------------------------------------------
+constexpr int kInvThreads = 256;
+
+template <int K, int CIN, int COUT>
+__device__ inline void stage_wt(const float* __restrict__ w, float* sw) {
+  constexpr int K3 = K * K * K, NW = K3 * CIN * COUT;
+  for (int i = threadIdx.x; i < NW; i += kInvThreads) {
+    const int q = i % K3, ci = (i / K3) % CIN, co = i / (K3 * CIN);   // source layout [co][ci][q]
+    sw[(q * COUT + co) * CIN + ci] = w[i];
+  }
+}
+
+template <int CIN, int COUT>
+__device__ inline void acc_tap(const float* __restrict__ sw_q, const float* __restrict__ dyrow, float* acc) {
+  float g[COUT];
+  load_vec<float, COUT>(dyrow, g);
+#pragma unroll
+  for (int co = 0; co < COUT; ++co)
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) acc[ci] = fmaf(sw_q[co * CIN + ci], g[co], acc[ci]);
+}
+
+template <int K, int CIN, int COUT>
+__global__ __launch_bounds__(kInvThreads) void bwd_dx_kernel(const uint32_t* __restrict__ gmap, int64_t n_p,
+                                                             uint32_t p_begin, uint32_t p_end,
+                                                             const uint32_t* __restrict__ inv_off,
+                                                             const uint32_t* __restrict__ inv_ent,
+                                                             const float* __restrict__ dy, const float* w_l,
+                                                             const float* w_fine, float* __restrict__ dx) {
+  constexpr int K3 = K * K * K, NW = K3 * CIN * COUT;
+  __shared__ float sw[NW], swf[NW];
+  stage_wt<K, CIN, COUT>(w_l, sw);
+  if (w_fine) stage_wt<K, CIN, COUT>(w_fine, swf);
+  __syncthreads();
+  const uint32_t s = p_begin + blockIdx.x * uint32_t(kInvThreads) + threadIdx.x;
+  if (s >= p_end) return;
+  float acc[CIN];
+#pragma unroll
+  for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
+  // the same-level reader of s through tap q sits at c_s - o: entry k^3-1-q of s's map
+  constexpr int CH = K3 <= 27 ? K3 : 25;
+  for (int q0 = 0; q0 < K3; q0 += CH) {
+    uint32_t g[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) g[j] = (q0 + j < K3) ? gmap[size_t(K3 - 1 - (q0 + j)) * size_t(n_p) + s] : kPad;
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if (g[j] != kPad && (g[j] >> 30) == 1) acc_tap<CIN, COUT>(sw + (q0 + j) * COUT * CIN, dy + size_t(g[j] & kIdxMask) * COUT, acc);
+  }
+  if (w_fine) {
+    const uint32_t b = inv_off[s], e = inv_off[s + 1];
+    for (uint32_t i = b; i < e; ++i) {
+      const uint32_t c = inv_ent[i];
+      acc_tap<CIN, COUT>(swf + (c % K3) * COUT * CIN, dy + size_t(c / K3) * COUT, acc);
+    }
+  }
+  store_vec<float, CIN>(dx + size_t(s) * CIN, acc);
+}
+
+template <int K, int CIN, int COUT>
+__global__ __launch_bounds__(kInvThreads) void bwd_dt_kernel(int64_t n_p, uint32_t t_begin, uint32_t t_end,
+                                                             const uint32_t* __restrict__ inv_off,
+                                                             const uint32_t* __restrict__ inv_ent,
+                                                             const float* __restrict__ dy, const float* w_L,
+                                                             float* __restrict__ dt) {
+  constexpr int K3 = K * K * K, NW = K3 * CIN * COUT;
+  __shared__ float sw[NW];
+  if (w_L) stage_wt<K, CIN, COUT>(w_L, sw);
+  __syncthreads();
+  const uint32_t t = t_begin + blockIdx.x * uint32_t(kInvThreads) + threadIdx.x;
+  if (t >= t_end) return;
+  float acc[CIN];
+#pragma unroll
+  for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
+  if (w_L) {
+    const uint32_t b = inv_off[n_p + t], e = inv_off[n_p + t + 1];
+    for (uint32_t i = b; i < e; ++i) {
+      const uint32_t c = inv_ent[i];
+      acc_tap<CIN, COUT>(sw + (c % K3) * COUT * CIN, dy + size_t(c / K3) * COUT, acc);
+    }
+  }
+  store_vec<float, CIN>(dt + size_t(t) * CIN, acc);
+}
+
+apr_status build_inverse_map(apr_handle* h, int k, hipStream_t s,
+                             apr_status (*alloc_u32)(apr_handle*, uint32_t**, int64_t),
+                             apr_status (*scan)(uint32_t*, int64_t, uint32_t*, hipStream_t), uint32_t* total_dev) {
+  const int gi = k == 3 ? 0 : 1;
+  const int k3 = k * k * k;
+  const int64_t n_pairs = h->n_p * k3, n_targets = h->n_p + h->n_t;
+  if (n_pairs >= (int64_t(1) << 32)) APR_FAIL(APR_EUNSUPPORTED, "apr_access_build: n_particles * k^3 must be < 2^32");
+  apr_status st = alloc_u32(h, &h->inv_off[gi], n_targets + 1);
+  if (st != APR_OK) return st;
+  uint32_t* cursor = nullptr;
+  if (hipMalloc(&cursor, size_t(n_targets + 1) * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    APR_FAIL(APR_ENOMEM, "hipMalloc failed (inverse map cursor)");
+  }
+  const uint32_t* gm = reinterpret_cast<const uint32_t*>(h->gmap[gi]);
+  const unsigned gp = unsigned((n_pairs + 255) / 256), gt = unsigned((n_targets + 255) / 256);
+  APR_HIP(hipMemsetAsync(h->inv_off[gi], 0, size_t(n_targets + 1) * 4, s));
+  hipLaunchKernelGGL(inv_count_kernel, dim3(gp), dim3(256), 0, s, gm, h->n_p, n_pairs, h->inv_off[gi]);
+  APR_HIP(hipGetLastError());
+  st = scan(h->inv_off[gi], n_targets + 1, total_dev, s);
+  if (st != APR_OK) {
+    (void)hipFree(cursor);
+    return st;
+  }
+  uint32_t n_ent = 0;
+  APR_HIP(hipMemcpyAsync(&n_ent, total_dev, 4, hipMemcpyDeviceToHost, s));
+  APR_HIP(hipStreamSynchronize(s));
+  st = alloc_u32(h, &h->inv_ent[gi], std::max<int64_t>(n_ent, 1));
+  if (st != APR_OK) {
+    (void)hipFree(cursor);
+    return st;
+  }
+  APR_HIP(hipMemsetAsync(cursor, 0, size_t(n_targets + 1) * 4, s));
+  hipLaunchKernelGGL(inv_fill_kernel, dim3(gp), dim3(256), 0, s, gm, h->n_p, n_pairs, k3, h->inv_off[gi], cursor,
+                     h->inv_ent[gi]);
+  hipLaunchKernelGGL(inv_sort_kernel, dim3(gt), dim3(256), 0, s, h->inv_off[gi], n_targets, h->inv_ent[gi]);
+  APR_HIP(hipGetLastError());
+  APR_HIP(hipStreamSynchronize(s));
+  (void)hipFree(cursor);
+  return APR_OK;
+}
+
 template <int K, int CI, int CO>
 static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, const float* dy, const float* w,
                                 float* dx, float* dt, hipStream_t s) {
   const Meta& m = h->meta;
   constexpr int K3 = K * K * K;
   auto wlev = [&](int l) { return w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * CO * CI * K3; };
+  const int gi = K == 3 ? 0 : 1;
+  const uint32_t* gm = reinterpret_cast<const uint32_t*>(gather_map(h, K));
+  uint32_t begin = 0;
   for (int l = m.l_min; l <= m.l_max; ++l) {
-    const int64_t rows = int64_t(m.dz[l]) * m.dx[l];
+    const uint32_t np_l = uint32_t(h->per_level_p[l]);
     const float* wf = (l + 1 <= m.l_max && h->per_level_p[l + 1]) ? wlev(l + 1) : nullptr;
-    hipLaunchKernelGGL((bwd_particle_kernel<K, CI, CO>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
-                       dim3(64 * kGWaves), 0, s, m, l, h->py, h->pend, gather_map(h, K), h->n_p, dy, wlev(l),
-                       wf, dx);
+    if (np_l)
+      hipLaunchKernelGGL((bwd_dx_kernel<K, CI, CO>), dim3((np_l + kInvThreads - 1) / kInvThreads), dim3(kInvThreads),
+                         0, s, gm, h->n_p, begin, begin + np_l, h->inv_off[gi], h->inv_ent[gi], dy, wlev(l), wf, dx);
+    begin += np_l;
   }
+  uint32_t tb = 0;
   for (int L = m.t_lo; L <= m.t_hi; ++L) {
-    const int64_t rows = int64_t(m.dz[L]) * m.dx[L];
-    const float* wL = (L >= m.l_min) ? wlev(L) : nullptr;
-    hipLaunchKernelGGL((bwd_tree_kernel<K, CI, CO>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
-                       dim3(64 * kGWaves), 0, s, m, L, h->py, h->pend, h->ty, h->tend, dy, wL, dt);
+    const uint32_t nt_l = uint32_t(h->per_level_t[L]);
+    const float* wL = (L >= m.l_min && h->per_level_p[L]) ? wlev(L) : nullptr;
+    if (nt_l)
+      hipLaunchKernelGGL((bwd_dt_kernel<K, CI, CO>), dim3((nt_l + kInvThreads - 1) / kInvThreads), dim3(kInvThreads),
+                         0, s, h->n_p, tb, tb + nt_l, h->inv_off[gi], h->inv_ent[gi], dy, wL, dt);
+    tb += nt_l;
   }
   // adjoint of the child means, coarsest tree level first
   for (int L = m.t_lo + 1; L <= m.t_hi; ++L) {
@@ -565,19 +629,86 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
   return APR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Weight gradient of a 16 -> 16, 3^3 layer on MFMA (v_mfma_f32_16x16x4_f32):
+// dW_l[co][ci][q] = sum_p dY[p][co] X[src(p, q)][ci] is, per tap, a 16 x 16
+// product with the particles as the reduction axis.  One block per run of
+// kWgtParticles particles of one level (the same units as the generic
+// kernel), the 27 taps split over its four waves: four particles per
+// instruction, A[m = co][k] = dY[p_k][co], B[k][n = ci] = X[src(p_k, q)][ci];
+// lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and D[4 (l / 16) + i]
+// [l % 16].  Up to 7 FP32 accumulators per lane; the sums go out as FP64
+// partials for the fixed-order reduction.
+// ---------------------------------------------------------------------------
+template <typename TX>
+__global__ __launch_bounds__(256) void bwd_weight_mfma16_kernel(int64_t p_begin, int64_t p_end,
+                                                                const uint32_t* __restrict__ gmap, int64_t n_p,
+                                                                const TX* __restrict__ x, const TX* __restrict__ tree,
+                                                                const float* __restrict__ dy,
+                                                                double* __restrict__ partial) {
+  constexpr int K3 = 27, NOUT = 16 * 16 * 27, TQ = 7;   // taps per wave: 7, 7, 7, 6
+  const int lane = int(threadIdx.x & 63), wave = int(threadIdx.x >> 6);
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int q0 = wave * TQ, nq = min(TQ, K3 - q0);
+  const int64_t u_b = p_begin + int64_t(blockIdx.x) * kWgtParticles;
+  const int64_t u_e = min(p_end, u_b + kWgtParticles);
+  mfma_f4 acc[TQ];
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) acc[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  // 16 particles per step: four groups of four, every gather of the step in flight together
+  for (int64_t p0 = u_b; p0 < u_e; p0 += 16) {
+    float a[4];
+    uint32_t g[4][TQ];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t p = p0 + 4 * j + kg;
+      const bool valid = p < u_e;
+      a[j] = valid ? dy[size_t(p) * 16 + r16] : 0.f;
+#pragma unroll
+      for (int t = 0; t < TQ; ++t)
+        g[j][t] = (valid && t < nq) ? gmap[size_t(q0 + t) * size_t(n_p) + size_t(p)] : kPad;
+    }
+    float b[4][TQ];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int t = 0; t < TQ; ++t)
+        b[j][t] = (g[j][t] != kPad)
+                      ? to_f32<TX>((((g[j][t] >> 30) == 3) ? tree : x)[size_t(g[j][t] & kIdxMask) * 16 + r16])
+                      : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int t = 0; t < TQ; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j][t], acc[t], 0, 0, 0);
+  }
+  double* out = partial + size_t(blockIdx.x) * NOUT;
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    if (t >= nq) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[((4 * kg + i) * 16 + r16) * K3 + q0 + t] = double(acc[t][i]);
+  }
+}
+
 template <int K, int CI, int CO, typename TX>
 static apr_status bwd_weight_impl(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                                   const float* dy, float* dw, double* ws, hipStream_t s) {
   const Meta& m = h->meta;
   constexpr int NOUT = CO * CI * K * K * K;
+  constexpr bool kMfma = K == 3 && CI == 16 && CO == 16;
   int64_t blk = 0;
   for (int l = m.l_min; l <= m.l_max; ++l) {
     const int nb = level_blocks(h, l);
     if (!nb) continue;
     const int64_t b = level_first(h, l);
-    hipLaunchKernelGGL((bwd_weight_partial_kernel<K, CI, CO, TX>), dim3(nb), dim3(kWgtThreads), 0, s, b,
-                       b + h->per_level_p[l], gather_map(h, K), h->n_p, static_cast<const TX*>(x),
-                       static_cast<const TX*>(tree), dy, ws + size_t(blk) * NOUT);
+    if constexpr (kMfma)
+      hipLaunchKernelGGL((bwd_weight_mfma16_kernel<TX>), dim3(nb), dim3(256), 0, s, b, b + h->per_level_p[l],
+                         reinterpret_cast<const uint32_t*>(gather_map(h, K)), h->n_p, static_cast<const TX*>(x),
+                         static_cast<const TX*>(tree), dy, ws + size_t(blk) * NOUT);
+    else
+      hipLaunchKernelGGL((bwd_weight_partial_kernel<K, CI, CO, TX>), dim3(nb), dim3(kWgtThreads), 0, s, b,
+                         b + h->per_level_p[l], gather_map(h, K), h->n_p, static_cast<const TX*>(x),
+                         static_cast<const TX*>(tree), dy, ws + size_t(blk) * NOUT);
     blk += nb;
   }
   const unsigned rg = unsigned((NOUT + 255) / 256);
