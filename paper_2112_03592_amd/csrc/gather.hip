@@ -216,12 +216,27 @@ __global__ __launch_bounds__(kWgtThreads) void bwd_weight_partial_kernel(
 }
 
 // dw[lo][o] = sum over the blocks [blk_b, blk_e) of partial[blk][o], in order
+// Fixed-order FP64 reduction of the block partials [blk_b, blk_e) in two
+// stages: chunks of kRedChunk partials are summed in place into the chunk's
+// first row (blockIdx.y = chunk), then the chunk sums in order.
+constexpr int kRedChunk = 64;
+
+__global__ void bwd_weight_chunk_kernel(double* __restrict__ partial, int64_t blk_b, int64_t blk_e, int nout) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j0 = blk_b + int64_t(blockIdx.y) * kRedChunk;
+  if (o >= nout || j0 >= blk_e) return;
+  const int64_t j1 = min(blk_e, j0 + kRedChunk);
+  double s = 0.0;
+  for (int64_t j = j0; j < j1; ++j) s += partial[size_t(j) * nout + o];
+  partial[size_t(j0) * nout + o] = s;
+}
+
 __global__ void bwd_weight_reduce_kernel(const double* __restrict__ partial, int64_t blk_b, int64_t blk_e,
                                          int nout, float* __restrict__ dw) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= nout) return;
   double s = 0.0;
-  for (int64_t j = blk_b; j < blk_e; ++j) s += partial[size_t(j) * nout + o];
+  for (int64_t j = blk_b; j < blk_e; j += kRedChunk) s += partial[size_t(j) * nout + o];
   dw[o] = float(s);
 }
 
@@ -344,6 +359,93 @@ static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// 16 -> 16 channels with FP32 rows on MFMA (v_mfma_f32_16x16x4_f32), for the
+// FP32 forward and for the same-level part of the data gradient (BWD: rows
+// are dY, taps flipped, only same-level entries, weights transposed).  The
+// reduction axis (16 input channels) is split as c = 4 kg + j over the lane
+// group kg = l / 16 and the four instructions j of a tap: lane l loads the
+// contiguous float4 R[src][4 kg .. 4 kg + 3] and holds A_j[m = l % 16][k = kg]
+// = R[src(p_m)][4 kg + j] and B_j[k = kg][n = l % 16] = Wt[4 kg + j][n]; D
+// lane layout as in the BF16 kernel.  B operands staged per block in LDS in
+// lane order; persistent waves over an XCD-contiguous tile range.
+// ---------------------------------------------------------------------------
+template <bool BWD, typename TY>
+__global__ __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(1, 4))) void mc16_f32_mfma_kernel(
+    const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end, const float* __restrict__ rows,
+    const float* __restrict__ tree, const float* __restrict__ w_level, const float* __restrict__ bias, int relu,
+    const TY* __restrict__ residual, TY* __restrict__ out) {
+  constexpr int K3 = 27;
+  __shared__ mfma_f4 sb[K3][64];
+  for (int j = threadIdx.x; j < K3 * 64; j += 64 * kMfmaWaves) {
+    const int q = j / 64, ln = j % 64, n = ln & 15, k = ln >> 4;
+    mfma_f4 v;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int c = 4 * k + jj;
+      v[jj] = BWD ? w_level[(c * 16 + n) * K3 + q] : w_level[(n * 16 + c) * K3 + q];
+    }
+    sb[q][ln] = v;
+  }
+  __syncthreads();
+  const uint32_t n_tiles = (p_end - p_begin + 15) / 16;
+  const uint32_t per = (n_tiles + 7) / 8;
+  const uint32_t tb = (blockIdx.x % 8) * per;
+  const uint32_t te = min(n_tiles, tb + per);
+  const uint32_t waves_per_xcd = (gridDim.x / 8) * kMfmaWaves;
+  const int lane = int(threadIdx.x & 63);
+  const int r16 = lane & 15, kg = lane >> 4;
+  const float bco = (!BWD && bias) ? bias[r16] : 0.f;
+  for (uint32_t tile = tb + (blockIdx.x / 8) * kMfmaWaves + threadIdx.x / 64; tile < te; tile += waves_per_xcd) {
+    asm volatile("" ::: "memory");   // keep the B operands in LDS (read per tile)
+    const uint32_t t0 = p_begin + tile * 16;
+    const uint32_t p = t0 + r16;
+    const bool valid = p < p_end;
+    uint32_t g[K3];
+#pragma unroll
+    for (int q = 0; q < K3; ++q) {
+      g[q] = valid ? gmap[size_t(BWD ? K3 - 1 - q : q) * size_t(n_p) + p] : kPad;
+      if (BWD && g[q] != kPad && (g[q] >> 30) != 1) g[q] = kPad;
+    }
+    // every gathered row of the tile in flight before the first product
+    mfma_f4 a[K3];
+#pragma unroll
+    for (int q = 0; q < K3; ++q) {
+      a[q] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+      if (g[q] != kPad)
+        a[q] = *reinterpret_cast<const mfma_f4*>(((!BWD && (g[q] >> 30) == 3) ? tree : rows) +
+                                                 size_t(g[q] & kIdxMask) * 16 + 4 * kg);
+    }
+    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < K3; ++q) {
+      const mfma_f4 b = sb[q][lane];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][j], b[j], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t pm = t0 + 4 * kg + i;
+      if (pm >= p_end) continue;
+      float o = acc[i] + bco;
+      if (!BWD && residual) o += to_f32<TY>(residual[size_t(pm) * 16 + r16]);
+      if (!BWD && relu) o = fmaxf(o, 0.f);
+      out[size_t(pm) * 16 + r16] = from_f32<TY>(o);
+    }
+  }
+}
+
+template <bool BWD, typename TY>
+static void launch_mc16_f32_mfma(const apr_handle* h, uint32_t begin, uint32_t np_l, const float* rows,
+                                 const float* tree, const float* wl, const float* bias, int relu, const TY* residual,
+                                 TY* out, hipStream_t s) {
+  const uint32_t tiles = (np_l + 15) / 16;
+  const uint32_t blocks_per_xcd = std::min<uint32_t>(kMfmaBlocksPerXcd, (tiles / 8 + kMfmaWaves) / kMfmaWaves);
+  hipLaunchKernelGGL((mc16_f32_mfma_kernel<BWD, TY>), dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)),
+                     dim3(64 * kMfmaWaves), 0, s, reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p, begin,
+                     begin + np_l, rows, tree, wl, bias, relu, residual, out);
+}
+
 template <int K, int CI, int CO, typename TX, typename TY>
 static void launch_mc_fwd(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                           const float* w, void* y, hipStream_t s) {
@@ -395,6 +497,29 @@ apr_status mc_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, c
     APR_HIP(hipGetLastError());
     return APR_OK;
   }
+  if (d->k == 3 && cin == 16 && cout == 16 && d->x_dtype == APR_F32 &&
+      ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 15) == 0) {
+    const Meta& m = h->meta;
+    uint32_t begin = 0;
+    for (int l = m.l_min; l <= m.l_max; ++l) {
+      const uint32_t np_l = uint32_t(h->per_level_p[l]);
+      const float* wl = w + size_t(d->n_wlevels == 1 ? 0 : l - m.l_min) * 16 * 16 * 27;
+      if (np_l) {
+        if (d->y_dtype == APR_F32)
+          launch_mc16_f32_mfma<false, float>(h, begin, np_l, static_cast<const float*>(x),
+                                             static_cast<const float*>(tree), wl, d->bias, d->relu,
+                                             static_cast<const float*>(d->residual), static_cast<float*>(y), s);
+        else
+          launch_mc16_f32_mfma<false, __hip_bfloat16>(h, begin, np_l, static_cast<const float*>(x),
+                                                      static_cast<const float*>(tree), wl, d->bias, d->relu,
+                                                      static_cast<const __hip_bfloat16*>(d->residual),
+                                                      static_cast<__hip_bfloat16*>(y), s);
+      }
+      begin += np_l;
+    }
+    APR_HIP(hipGetLastError());
+    return APR_OK;
+  }
   if (d->k == 3) {
     APR_CH_DISPATCH(1, 1, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
     APR_CH_DISPATCH(1, 16, return mc_fwd_dtypes<3, CI, CO>(h, d, x, tree, w, y, s))
@@ -439,14 +564,18 @@ __global__ void inv_fill_kernel(const uint32_t* __restrict__ gmap, int64_t n_p, 
   ent[off[t] + atomicAdd(&cursor[t], 1u)] = p * uint32_t(k3) + q;
 }
 
-__global__ void inv_sort_kernel(const uint32_t* __restrict__ off, int64_t n_targets, uint32_t* __restrict__ ent) {
+// readers of one source ordered by (tap, reader)
+__global__ void inv_sort_kernel(const uint32_t* __restrict__ off, int64_t n_targets, int k3,
+                                uint32_t* __restrict__ ent) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_targets) return;
   const uint32_t b = off[t], e = off[t + 1];
+  auto key = [&](uint32_t c) { return (uint64_t(c % uint32_t(k3)) << 32) | (c / uint32_t(k3)); };
   for (uint32_t i = b + 1; i < e; ++i) {
     const uint32_t v = ent[i];
+    const uint64_t kv = key(v);
     uint32_t j = i;
-    while (j > b && ent[j - 1] > v) {
+    while (j > b && key(ent[j - 1]) > kv) {
       ent[j] = ent[j - 1];
       --j;
     }
@@ -483,7 +612,42 @@ __device__ inline void acc_tap(const float* __restrict__ sw_q, const float* __re
     for (int ci = 0; ci < CIN; ++ci) acc[ci] = fmaf(sw_q[co * CIN + ci], g[co], acc[ci]);
 }
 
+// readers of one source from the inverse map, taps in the same order in
+// every lane: the dY rows of the lane's readers through tap q are summed,
+// then one product with W_q^T whose weights every lane reads at the same LDS
+// address; taps no lane of the wave reads are skipped
 template <int K, int CIN, int COUT>
+__device__ inline void acc_inverse(const uint32_t* __restrict__ inv_ent, uint32_t b, uint32_t e,
+                                   const float* __restrict__ dy, const float* __restrict__ sw, float* acc) {
+  constexpr int K3 = K * K * K;
+  uint32_t i = b;
+  uint32_t c = i < e ? inv_ent[i] : 0xffffffffu;
+  for (int q = 0; q < K3; ++q) {
+    float g[COUT];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) g[co] = 0.f;
+    bool any = false;
+    while (i < e && int(c % K3) == q) {
+      float v[COUT];
+      load_vec<float, COUT>(dy + size_t(c / K3) * COUT, v);
+#pragma unroll
+      for (int co = 0; co < COUT; ++co) g[co] += v[co];
+      any = true;
+      ++i;
+      c = i < e ? inv_ent[i] : 0xffffffffu;
+    }
+    if (!__any(any)) continue;
+    const float* w = sw + q * COUT * CIN;
+#pragma unroll
+    for (int co = 0; co < COUT; ++co)
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci) acc[ci] = fmaf(w[co * CIN + ci], g[co], acc[ci]);
+  }
+}
+
+// SAME = false: only the readers from the inverse map, added to dx (the
+// same-level part was written by the MFMA kernel)
+template <int K, int CIN, int COUT, bool SAME>
 __global__ __launch_bounds__(kInvThreads) void bwd_dx_kernel(const uint32_t* __restrict__ gmap, int64_t n_p,
                                                              uint32_t p_begin, uint32_t p_end,
                                                              const uint32_t* __restrict__ inv_off,
@@ -491,18 +655,23 @@ __global__ __launch_bounds__(kInvThreads) void bwd_dx_kernel(const uint32_t* __r
                                                              const float* __restrict__ dy, const float* w_l,
                                                              const float* w_fine, float* __restrict__ dx) {
   constexpr int K3 = K * K * K, NW = K3 * CIN * COUT;
-  __shared__ float sw[NW], swf[NW];
-  stage_wt<K, CIN, COUT>(w_l, sw);
+  __shared__ float sw[SAME ? NW : 1], swf[NW];
+  if (SAME) stage_wt<K, CIN, COUT>(w_l, sw);
   if (w_fine) stage_wt<K, CIN, COUT>(w_fine, swf);
   __syncthreads();
   const uint32_t s = p_begin + blockIdx.x * uint32_t(kInvThreads) + threadIdx.x;
   if (s >= p_end) return;
+  if (!SAME && !(w_fine && inv_off[s + 1] > inv_off[s])) return;
   float acc[CIN];
+  if (SAME) {
 #pragma unroll
-  for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
+    for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
+  } else {
+    load_vec<float, CIN>(dx + size_t(s) * CIN, acc);
+  }
   // the same-level reader of s through tap q sits at c_s - o: entry k^3-1-q of s's map
   constexpr int CH = K3 <= 27 ? K3 : 25;
-  for (int q0 = 0; q0 < K3; q0 += CH) {
+  for (int q0 = 0; SAME && q0 < K3; q0 += CH) {
     uint32_t g[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) g[j] = (q0 + j < K3) ? gmap[size_t(K3 - 1 - (q0 + j)) * size_t(n_p) + s] : kPad;
@@ -510,13 +679,7 @@ __global__ __launch_bounds__(kInvThreads) void bwd_dx_kernel(const uint32_t* __r
     for (int j = 0; j < CH; ++j)
       if (g[j] != kPad && (g[j] >> 30) == 1) acc_tap<CIN, COUT>(sw + (q0 + j) * COUT * CIN, dy + size_t(g[j] & kIdxMask) * COUT, acc);
   }
-  if (w_fine) {
-    const uint32_t b = inv_off[s], e = inv_off[s + 1];
-    for (uint32_t i = b; i < e; ++i) {
-      const uint32_t c = inv_ent[i];
-      acc_tap<CIN, COUT>(swf + (c % K3) * COUT * CIN, dy + size_t(c / K3) * COUT, acc);
-    }
-  }
+  if (w_fine) acc_inverse<K, CIN, COUT>(inv_ent, inv_off[s], inv_off[s + 1], dy, swf, acc);
   store_vec<float, CIN>(dx + size_t(s) * CIN, acc);
 }
 
@@ -535,13 +698,7 @@ __global__ __launch_bounds__(kInvThreads) void bwd_dt_kernel(int64_t n_p, uint32
   float acc[CIN];
 #pragma unroll
   for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
-  if (w_L) {
-    const uint32_t b = inv_off[n_p + t], e = inv_off[n_p + t + 1];
-    for (uint32_t i = b; i < e; ++i) {
-      const uint32_t c = inv_ent[i];
-      acc_tap<CIN, COUT>(sw + (c % K3) * COUT * CIN, dy + size_t(c / K3) * COUT, acc);
-    }
-  }
+  if (w_L) acc_inverse<K, CIN, COUT>(inv_ent, inv_off[n_p + t], inv_off[n_p + t + 1], dy, sw, acc);
   store_vec<float, CIN>(dt + size_t(t) * CIN, acc);
 }
 
@@ -580,7 +737,7 @@ apr_status build_inverse_map(apr_handle* h, int k, hipStream_t s,
   APR_HIP(hipMemsetAsync(cursor, 0, size_t(n_targets + 1) * 4, s));
   hipLaunchKernelGGL(inv_fill_kernel, dim3(gp), dim3(256), 0, s, gm, h->n_p, n_pairs, k3, h->inv_off[gi], cursor,
                      h->inv_ent[gi]);
-  hipLaunchKernelGGL(inv_sort_kernel, dim3(gt), dim3(256), 0, s, h->inv_off[gi], n_targets, h->inv_ent[gi]);
+  hipLaunchKernelGGL(inv_sort_kernel, dim3(gt), dim3(256), 0, s, h->inv_off[gi], n_targets, k3, h->inv_ent[gi]);
   APR_HIP(hipGetLastError());
   APR_HIP(hipStreamSynchronize(s));
   (void)hipFree(cursor);
@@ -599,9 +756,19 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
   for (int l = m.l_min; l <= m.l_max; ++l) {
     const uint32_t np_l = uint32_t(h->per_level_p[l]);
     const float* wf = (l + 1 <= m.l_max && h->per_level_p[l + 1]) ? wlev(l + 1) : nullptr;
-    if (np_l)
-      hipLaunchKernelGGL((bwd_dx_kernel<K, CI, CO>), dim3((np_l + kInvThreads - 1) / kInvThreads), dim3(kInvThreads),
-                         0, s, gm, h->n_p, begin, begin + np_l, h->inv_off[gi], h->inv_ent[gi], dy, wlev(l), wf, dx);
+    if (np_l) {
+      if constexpr (K == 3 && CI == 16 && CO == 16) {
+        launch_mc16_f32_mfma<true, float>(h, begin, np_l, dy, nullptr, wlev(l), nullptr, 0, nullptr, dx, s);
+        if (wf)
+          hipLaunchKernelGGL((bwd_dx_kernel<K, CI, CO, false>), dim3((np_l + kInvThreads - 1) / kInvThreads),
+                             dim3(kInvThreads), 0, s, gm, h->n_p, begin, begin + np_l, h->inv_off[gi], h->inv_ent[gi],
+                             dy, wlev(l), wf, dx);
+      } else {
+        hipLaunchKernelGGL((bwd_dx_kernel<K, CI, CO, true>), dim3((np_l + kInvThreads - 1) / kInvThreads),
+                           dim3(kInvThreads), 0, s, gm, h->n_p, begin, begin + np_l, h->inv_off[gi], h->inv_ent[gi],
+                           dy, wlev(l), wf, dx);
+      }
+    }
     begin += np_l;
   }
   uint32_t tb = 0;
@@ -641,7 +808,7 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
 // partials for the fixed-order reduction.
 // ---------------------------------------------------------------------------
 template <typename TX>
-__global__ __launch_bounds__(256) void bwd_weight_mfma16_kernel(int64_t p_begin, int64_t p_end,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void bwd_weight_mfma16_kernel(int64_t p_begin, int64_t p_end,
                                                                 const uint32_t* __restrict__ gmap, int64_t n_p,
                                                                 const TX* __restrict__ x, const TX* __restrict__ tree,
                                                                 const float* __restrict__ dy,
@@ -655,12 +822,13 @@ __global__ __launch_bounds__(256) void bwd_weight_mfma16_kernel(int64_t p_begin,
   mfma_f4 acc[TQ];
 #pragma unroll
   for (int t = 0; t < TQ; ++t) acc[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-  // 16 particles per step: four groups of four, every gather of the step in flight together
-  for (int64_t p0 = u_b; p0 < u_e; p0 += 16) {
-    float a[4];
-    uint32_t g[4][TQ];
+  // 32 particles per step: eight groups of four, every gather of the step in flight together
+  constexpr int NJ = 8;
+  for (int64_t p0 = u_b; p0 < u_e; p0 += 4 * NJ) {
+    float a[NJ];
+    uint32_t g[NJ][TQ];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       const int64_t p = p0 + 4 * j + kg;
       const bool valid = p < u_e;
       a[j] = valid ? dy[size_t(p) * 16 + r16] : 0.f;
@@ -668,16 +836,16 @@ __global__ __launch_bounds__(256) void bwd_weight_mfma16_kernel(int64_t p_begin,
       for (int t = 0; t < TQ; ++t)
         g[j][t] = (valid && t < nq) ? gmap[size_t(q0 + t) * size_t(n_p) + size_t(p)] : kPad;
     }
-    float b[4][TQ];
+    float b[NJ][TQ];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int t = 0; t < TQ; ++t)
         b[j][t] = (g[j][t] != kPad)
                       ? to_f32<TX>((((g[j][t] >> 30) == 3) ? tree : x)[size_t(g[j][t] & kIdxMask) * 16 + r16])
                       : 0.f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int t = 0; t < TQ; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j][t], acc[t], 0, 0, 0);
   }
@@ -712,14 +880,19 @@ static apr_status bwd_weight_impl(const apr_handle* h, const apr_conv_desc* d, c
     blk += nb;
   }
   const unsigned rg = unsigned((NOUT + 255) / 256);
+  auto reduce = [&](int64_t bb, int64_t be, float* out) {
+    const unsigned nc = unsigned((be - bb + kRedChunk - 1) / kRedChunk);
+    if (nc > 0)
+      hipLaunchKernelGGL(bwd_weight_chunk_kernel, dim3(rg, nc), dim3(256), 0, s, ws, bb, be, NOUT);
+    hipLaunchKernelGGL(bwd_weight_reduce_kernel, dim3(rg), dim3(256), 0, s, ws, bb, be, NOUT, out);
+  };
   if (d->n_wlevels == 1) {
-    hipLaunchKernelGGL(bwd_weight_reduce_kernel, dim3(rg), dim3(256), 0, s, ws, int64_t(0), blk, NOUT, dw);
+    reduce(0, blk, dw);
   } else {
     int64_t bb = 0;
     for (int l = m.l_min; l <= m.l_max; ++l) {
       const int nb = level_blocks(h, l);
-      hipLaunchKernelGGL(bwd_weight_reduce_kernel, dim3(rg), dim3(256), 0, s, ws, bb, bb + nb, NOUT,
-                         dw + size_t(l - m.l_min) * NOUT);
+      reduce(bb, bb + nb, dw + size_t(l - m.l_min) * NOUT);
       bb += nb;
     }
   }
