@@ -52,9 +52,10 @@ def conv_bytes(n_p, n_t, rows, trows, bv=4):
 
 
 def fill_bytes(n_p, n_t, rows, trows, bv=4):
-    """Tree fill: particle values + y read, tree y read, tree values written
-    and read back once as children of the next coarser level."""
-    return n_p * (bv + 2) + n_t * (2 + bv + bv) + 4 * (rows + trows)
+    """Tree fill over the child map: the map (8 x u32 per node) and every
+    particle value read once, tree values written and read back once as
+    children of the next coarser level."""
+    return n_p * bv + n_t * (32 + 2 * bv)
 
 
 def cpu_baseline(inp, sample: int):

@@ -34,11 +34,12 @@ constexpr int kRowIdCap = 3584;  // patch items per chunk with a stored source r
 // time, so resident waves decide its speed: the 3^3 patch lets three
 // workgroups share a CU once registers are capped for six waves per SIMD;
 // the larger 5^3 patch allows two, so those workgroups are 1024 threads wide
-// (eight waves per SIMD) with fewer elements in flight per thread.
+// (eight waves per SIMD).  Elements in flight per thread are set so that
+// nothing spills under those caps (spilled registers go through HBM).
 template <int K>
 struct ConvShape {
   static constexpr int kThreads = K == 3 ? 512 : 1024;
-  static constexpr int kBatch = K == 3 ? 4 : 2;        // independent elements per thread in flight
+  static constexpr int kBatch = K == 3 ? 2 : 1;        // independent elements per thread in flight
   static constexpr int kWavesPerSimd = K == 3 ? 6 : 8;
 };
 
