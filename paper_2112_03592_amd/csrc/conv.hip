@@ -29,7 +29,6 @@ namespace apr {
 
 constexpr int kYC = 64;          // output cells per chunk along y
 constexpr int kBig = 1 << 28;    // y of an element past the end of its row
-constexpr int kRowIdCap = 3584;  // patch items per chunk with a stored source row
 // Launch shape per stencil size.  The kernel waits on memory most of the
 // time, so resident waves decide its speed: the 3^3 patch lets three
 // workgroups share a CU once registers are capped for six waves per SIMD;
@@ -138,9 +137,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
   __shared__ int16_t cbase[NCR];            // coarse row -> halo row of target q = 0
   __shared__ uint32_t op[NC], oe[NC], opd[NC], ocnt[NC], opre[2][NC + 1];
   __shared__ int rymax[NC], rnext[NC];      // per centre row: last listed y, next y
-  __shared__ uint8_t crow[NOUT];            // centre row of each listing item
   __shared__ uint16_t o_pos[NOUT];          // (centre row << 6) | (y - y0), or kUnlisted
-  __shared__ uint16_t srow[kRowIdCap];      // source row of each patch item
   __shared__ int s_y0;
 
   const int tid = threadIdx.x;
@@ -221,11 +218,6 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
   if (wave == 0) {
     if (lane == 0) s_y0 = ty0;   // first y of the tile's particles, from the tile list
     wave_scan_into<1>(opre[0], NC, [&](int c) { return min(oe[c] - op[c], uint32_t(OCAP)); });
-    wave_lds_sync();
-    for (int c = 0; c < NC; ++c) {
-      const uint32_t b = opre[0][c], n = opre[0][c + 1] - b;
-      for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
-    }
   }
   lds_barrier();
 
@@ -249,7 +241,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
       for (int u = 0; u < kBatch; ++u) {
         const uint32_t it = base + u * NT;
         const bool ok = it < nb;
-        cc[u] = ok ? int(crow[it]) : 0;
+        cc[u] = ok ? find_row(ocap, NC, it) : 0;
         jj[u] = ok ? it - ocap[cc[u]] : 0u;
         ii[u] = op[cc[u]] + jj[u];
         yv[u] = ok ? int(py[ii[u]]) : 0;
@@ -285,11 +277,11 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
     const int wlo = y0 - R, whi = ymax_c + R;
     const int drop = (ynx == int(kNoY)) ? whi + 1 : ynx - R;   // cells below `drop` are never needed again
 
-    // ---- C0 (no memory round): wave 0 advances the centre pointers, sizes
-    // the next chunk's centre items, and sizes every source row's share of
-    // this window (y grows by >= 1 per element; a coarse element covers two
-    // cells); the other waves pad y outside the image
-    if (wave == 0) {
+    // ---- C0 (no memory round): wave 1 advances the centre pointers and sizes
+    // the next chunk's centre items; wave 0 sizes every source row's share
+    // of this window (y grows by >= 1 per element; a coarse element covers
+    // two cells); the other waves pad y outside the image
+    if (wave == 1) {
       if (lane < uint32_t(NC)) {
         opd[lane] = op[lane];
         op[lane] += ocnt[lane];
@@ -297,6 +289,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
       }
       wave_lds_sync();
       wave_scan_into<1>(opre[par ^ 1], NC, [&](int c) { return min(oe[c] - op[c], uint32_t(OCAP)); });
+    } else if (wave == 0) {
       wave_scan_into<ES>(spre, NSRC, [&](int sr) -> uint32_t {
         if (sp[sr] >= se[sr]) return 0u;
         const int last = (sr >= 2 * NH) ? (whi >> 1) : whi;
@@ -305,24 +298,10 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
       });
     } else if (wlo < 0 || whi >= Dy) {   // y outside the image is zero padding
       const int span = whi - wlo + 1;
-      for (int j = tid - 64; j < NH * span; j += NT - 64) {
+      for (int j = tid - 128; j < NH * span; j += NT - 128) {
         const int h = j / span, p = j % span;
         const int yy = wlo + p;
         if (yy < 0 || yy >= Dy) patch[h * PY + p] = pad;
-      }
-    }
-    lds_barrier();
-    // source row of every patch item (items past kRowIdCap search instead);
-    // centre row of every next-chunk listing item
-    for (int r = wave; r < NSRC; r += NW) {
-      const uint32_t b = spre[r], e = min(spre[r + 1], uint32_t(kRowIdCap));
-      for (uint32_t j = b + lane; j < e; j += 64) srow[j] = uint16_t(r);
-    }
-    {
-      const uint32_t* nc = opre[par ^ 1];
-      for (int c = wave; c < NC; c += NW) {
-        const uint32_t b = nc[c], n = nc[c + 1] - b;
-        for (uint32_t j = lane; j < n; j += 64) crow[b + j] = uint8_t(c);
       }
     }
     lds_barrier();
@@ -339,7 +318,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
       for (int u = 0; u < kBatch; ++u) {
         const uint32_t it = base + u * NT;
         const bool ok = it < nsf;
-        ss[u] = ok ? (it < uint32_t(kRowIdCap) ? int(srow[it]) : find_row(spre, NSRC, it)) : 0;
+        ss[u] = ok ? find_row(spre, NSRC, it) : 0;
         jj[u] = ok ? it - spre[ss[u]] : 0u;
         ii[u] = sp[ss[u]] + jj[u];
         const bool istree = ss[u] >= NH;
@@ -373,7 +352,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
       for (int u = 0; u < kBatch; ++u) {
         const uint32_t it = base + u * NT;
         const bool ok = it < ns;
-        ss[u] = ok ? (it < uint32_t(kRowIdCap) ? int(srow[it]) : find_row(spre, NSRC, it)) : 2 * NH;
+        ss[u] = ok ? find_row(spre, NSRC, it) : 2 * NH;
         jj[u] = ok ? it - spre[ss[u]] : 0u;
         ii[u] = sp[ss[u]] + jj[u];
         yv[u] = ok ? int(py[ii[u]]) : kBig;
