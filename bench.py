@@ -185,7 +185,7 @@ def surrogate_inputs(which: str):
     return inputs
 
 
-def surrogate_leg(which: str, inputs, reps: int = 3):
+def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WEIGHTS):
     """Plain 10-iteration APR Richardson-Lucy against the surrogate (start
     iterations + network + monitor, plus the plain iteration when the monitor
     rejects) on a batch of deconvolution APRs; relative L2 error of the
@@ -195,7 +195,7 @@ def surrogate_leg(which: str, inputs, reps: int = 3):
     from paper_2112_03592_amd import apr as G
     from paper_2112_03592_amd import surrogate as N
     edges = SURROGATE_EVAL[which]
-    sur = N.load_surrogate(SURROGATE_WEIGHTS)
+    sur = N.load_surrogate(weights)
     ws = G.Workspace(16)
     rec = {"edges": list(edges), "n_particles": [], "plain_ms": [], "surrogate_ms": [], "error": [],
            "monitor": [], "fallback": []}
@@ -247,6 +247,7 @@ def main():
     ap.add_argument("--surrogate-eval", default="small", choices=["small", "full", "none"],
                     help="batch of the surrogate-vs-plain Richardson-Lucy comparison")
     ap.add_argument("--no-layers", action="store_true", help="skip the gather-path layer timings")
+    ap.add_argument("--surrogate-weights", default=SURROGATE_WEIGHTS, help="trained surrogate (.npz)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate comparison and print its record (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -273,14 +274,15 @@ def main():
     from paper_2112_03592_amd import apr as G
 
     sur_inputs = None
-    if args.surrogate_eval != "none" and os.path.exists(SURROGATE_WEIGHTS):
+    if args.surrogate_eval != "none" and os.path.exists(args.surrogate_weights):
         sur_inputs = surrogate_inputs(args.surrogate_eval)
 
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     if args.surrogate_only:
-        print(json.dumps(surrogate_leg(args.surrogate_eval, sur_inputs) if sur_inputs is not None
+        print(json.dumps(surrogate_leg(args.surrogate_eval, sur_inputs, weights=args.surrogate_weights)
+                         if sur_inputs is not None
                          else {"skipped": "no trained weights or --surrogate-eval none"}), flush=True)
         return
     log(f"workload {args.workload}: generating / loading input")
@@ -392,7 +394,7 @@ def main():
         out["layers"] = layers_leg(inp)
     if sur_inputs is not None:
         log(f"surrogate leg ({args.surrogate_eval} batch)")
-        out["surrogate"] = surrogate_leg(args.surrogate_eval, sur_inputs)
+        out["surrogate"] = surrogate_leg(args.surrogate_eval, sur_inputs, weights=args.surrogate_weights)
     elif args.surrogate_eval != "none":
         out["surrogate"] = {"skipped": "no trained weights (python -m paper_2112_03592_amd.train_surrogate)"}
     if not args.no_cpu_baseline:

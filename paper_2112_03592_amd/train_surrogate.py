@@ -51,9 +51,9 @@ def device_cases(apr_inputs, rl: N.RichardsonLucy, n_iter: int):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--n-pre", type=int, default=4)
+    ap.add_argument("--n-pre", type=int, default=3)
     ap.add_argument("--layers", type=int, default=4)
     ap.add_argument("--channels", type=int, default=16)
     ap.add_argument("--seed", type=int, default=0)
