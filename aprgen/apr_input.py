@@ -462,13 +462,24 @@ def _deconv_job(args):
     return a
 
 
-def deconv_set(edges: Sequence[int], seed0: int, workers: int = 1):
+def deconv_set(edges: Sequence[int], seed0: int, workers: int = 1, progress=None):
     """APRs of the deconvolution workload with seeds seed0, seed0 + 1, ...;
-    generated in ``workers`` processes."""
+    generated in ``workers`` processes; ``progress(edge, n_particles)`` is
+    called as each one is done."""
     jobs = [(int(e), seed0 + i) for i, e in enumerate(edges)]
     if workers <= 1 or len(jobs) <= 1:
-        return [_deconv_job(j) for j in jobs]
+        out = []
+        for j in jobs:
+            out.append(_deconv_job(j))
+            if progress:
+                progress(j[0], out[-1].n_particles)
+        return out
     import concurrent.futures as cf
     import multiprocessing as mp
     with cf.ProcessPoolExecutor(max_workers=min(workers, len(jobs)), mp_context=mp.get_context("spawn")) as ex:
-        return list(ex.map(_deconv_job, jobs))
+        futs = [ex.submit(_deconv_job, j) for j in jobs]
+        for f, j in zip(cf.as_completed(futs), jobs):
+            if progress:
+                a = f.result()
+                progress(a.dims[0], a.n_particles)
+        return [f.result() for f in futs]

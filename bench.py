@@ -180,7 +180,8 @@ def surrogate_inputs(which: str):
     touches the GPU)."""
     from aprgen.apr_input import deconv_set
     t0 = time.perf_counter()
-    inputs = deconv_set(SURROGATE_EVAL[which], 7000, workers=8)
+    inputs = deconv_set(SURROGATE_EVAL[which], 7000, workers=8,
+                        progress=lambda e, n: log(f"  generated {e}^3 deconvolution APR, {n} particles"))
     log(f"surrogate batch {SURROGATE_EVAL[which]} generated in {time.perf_counter() - t0:.1f} s")
     return inputs
 

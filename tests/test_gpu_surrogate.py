@@ -259,11 +259,11 @@ TRAINED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 
 @pytest.mark.parametrize("edge,seed", [(96, 8001), (112, 8003), (128, 8002)])
 def test_trained_surrogate_against_fp64_oracle_rl10(edge, seed):
-    """Held-out deconvolution APR: the trained network's estimate lies within
-    2e-2 of the FP64 oracle's 10 Richardson-Lucy iterations and gains over its
-    start (the over-relaxed iterations alone), over the same network
-    untrained, and over the input; what the surrogate returns (the estimate
-    when the monitor accepts it, else the plain iteration) is within 2e-2."""
+    """Held-out deconvolution APR against the FP64 oracle's 10 Richardson-Lucy
+    iterations: the trained network's estimate gains over its start (the
+    over-relaxed iterations alone), over the same network untrained, and over
+    the input; an estimate the monitor accepts is within 2e-2, so what the
+    surrogate returns (the estimate, else the plain iteration) always is."""
     say("trained", edge, seed)
     inp = sphere_apr(deconv_config(edge, seed))
     la = linear_access(inp)
@@ -290,11 +290,12 @@ def test_trained_surrogate_against_fp64_oracle_rl10(edge, seed):
         f"{err(s_fresh):.4f} input {err(u):.4f} plain FP32 {err(plain):.2e}; monitor {m:.4f} tau {sur.tau:.4f} "
         f"fallback {res.fallback}")
     assert err(plain) < 1e-4
-    assert err(est) <= 2e-2
-    assert err(est) < 0.75 * err(base)
-    assert err(est) < 0.75 * err(s_fresh)
+    assert err(est) < 0.5 * err(base)
+    assert err(est) < 0.5 * err(s_fresh)
     assert err(est) < 0.1 * err(u)
     assert res.monitor == m and res.fallback == (m > sur.tau)
+    if not res.fallback:
+        assert err(est) <= 2e-2
     assert err(got) <= 2e-2
     assert np.array_equal(got, plain if res.fallback else est)
 
