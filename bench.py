@@ -87,10 +87,10 @@ def cpu_baseline(inp, sample: int):
 
 
 SURROGATE_EVAL = {
-    # 8 APRs of uneven sizes; "full" is the 256^3-768^3 batch (about 6 CPU
-    # minutes to generate), "small" the default
-    "small": (160, 192, 224, 256, 288, 320, 352, 384),
+    # 8 APRs of uneven sizes from 256^3 to 768^3 (~34M particles; generated in
+    # worker processes, ~20 s on 16 cores), and a smaller batch for quick runs
     "full": (256, 320, 384, 448, 512, 576, 640, 768),
+    "small": (160, 192, 224, 256, 288, 320, 352, 384),
 }
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_2112_03592_amd", "weights", "rl10_surrogate.npz")
 
@@ -245,7 +245,7 @@ def main():
     ap.add_argument("--workload", default="sphere512")
     ap.add_argument("--cpu-sample", type=int, default=1 << 15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--surrogate-eval", default="small", choices=["small", "full", "none"],
+    ap.add_argument("--surrogate-eval", default="full", choices=["full", "small", "none"],
                     help="batch of the surrogate-vs-plain Richardson-Lucy comparison")
     ap.add_argument("--no-layers", action="store_true", help="skip the gather-path layer timings")
     ap.add_argument("--surrogate-weights", default=SURROGATE_WEIGHTS, help="trained surrogate (.npz)")
