@@ -51,8 +51,8 @@ typedef int32_t apr_status;
 /* apr_access_desc.flags */
 #define APR_VALIDATE_PARTITION 1u  /* check on the device that the cells partition the image */
 #define APR_VALIDATE_BALANCE 2u    /* check 26-neighbour 2:1 level balance */
-#define APR_BUILD_GATHER3 4u       /* also build the 3^3 gather map (multichannel, backward) */
-#define APR_BUILD_GATHER5 8u       /* also build the 5^3 gather map */
+#define APR_BUILD_GATHER3 4u       /* also build the 3^3 gather map and its inverse (multichannel, backward) */
+#define APR_BUILD_GATHER5 8u       /* also build the 5^3 gather map and its inverse */
 
 #define APR_MAX_LEVELS 17          /* levels 0..16 (y_dim <= 65535) */
 
@@ -93,8 +93,9 @@ typedef struct apr_handle apr_handle;
  * the level's y size), copies them to the current HIP device, derives the APR
  * tree (all interior nodes, Section 3.4: for every tree row the sorted union of
  * y/2 over the particles and tree nodes of its 2x2 child rows, finest level
- * first) and the list of non-empty convolution tiles (the non-empty-row
- * pre-pass of Section 5.2).  Optional device validation per `desc->flags`
+ * first), the list of non-empty convolution tiles (the non-empty-row
+ * pre-pass of Section 5.2, with each tile's first particle y) and the child
+ * list of every tree node (which apr_fill_tree gathers over).  Optional device validation per `desc->flags`
  * returns APR_EPARTITION / APR_EUNBALANCED.  Synchronizes `stream` once before
  * returning.  The handle owns all its device memory; it is immutable after
  * the build and may be used from several streams.  Free with
@@ -179,12 +180,16 @@ apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, 
  * kernels; every other request (multichannel Y[p,co] = b[co] + sum_{ci,o}
  * W_l[co][ci][o] V_l[ci](c_p + o)) runs on the gather map and needs the handle
  * built with APR_BUILD_GATHER3 / APR_BUILD_GATHER5 for d->k.  Supported
- * (c_in, c_out): k = 3: (1,1) (1,16) (16,16) (16,1) (2,3); k = 5: (1,1) (2,3). */
+ * (c_in, c_out): k = 3: (1,1) (1,16) (16,16) (16,1) (2,3); k = 5: (1,1) (2,3).
+ * k = 3, 16 -> 16 runs on matrix cores: with BF16 x and tree (8-byte aligned)
+ * the weights are rounded to BF16 (FP32 accumulation); with FP32 x and tree
+ * (16-byte aligned) FP32 throughout. */
 
 /* Gradient of apr_conv with respect to x (the transpose of the linear map
  * x -> y, bias excluded): same-level taps, taps of level-(l+1) particles that
  * read a level-l particle as their coarser source, and tree taps routed down
- * through the child means (adjoint of Section 3.4's average).  dy: device FP32
+ * through the child means (adjoint of Section 3.4's average).  The last two
+ * come from the inverse of the gather map, built with it.  dy: device FP32
  * [N_p][c_out]; w: FP32 weights as in apr_conv; dx: device FP32 [N_p][c_in]
  * (overwritten); dtree: device FP32 [N_t][c_in] scratch.  Needs the gather map
  * for d->k.  Deterministic.  Asynchronous. */

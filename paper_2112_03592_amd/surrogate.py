@@ -70,28 +70,32 @@ def apr_conv_layer(acc: G.AprAccess, x: torch.Tensor, w: torch.Tensor, b: torch.
 # ---------------------------------------------------------------------------
 
 class RichardsonLucy:
-    """``apr_richardson_lucy`` with the restricted PSF stencils and the
-    workspace of each access structure kept between calls."""
+    """``apr_richardson_lucy`` with the restricted PSF stencils kept per level
+    range and one workspace grown to the largest APR seen."""
 
     def __init__(self, psf: np.ndarray, eps_rel: float = 1e-12):
         self.psf = np.asarray(psf, np.float64)
         self.k = self.psf.shape[-1]
         self.eps_rel = eps_rel
-        self._cache: Dict[int, Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = {}
+        self._stencils: Dict[Tuple[int, int], Tuple[torch.Tensor, torch.Tensor]] = {}
+        self._ws: Optional[torch.Tensor] = None
 
     def _prep(self, acc: G.AprAccess, device):
-        key = id(acc)
-        if key not in self._cache:
+        key = (acc.l_min, acc.l_max)
+        if key not in self._stencils:
             w = torch.from_numpy(G.stencil_levels(self.psf, "restrict", self.k, acc.l_min, acc.l_max)).to(device)
             wf = torch.from_numpy(G.stencil_levels(self.psf, "restrict", self.k, acc.l_min, acc.l_max,
                                                    flip=True)).to(device)
-            nbytes = int(acc._lib.apr_richardson_lucy_workspace(acc.handle))
-            ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-            self._cache[key] = (w, wf, ws)
-        return self._cache[key]
+            self._stencils[key] = (w, wf)
+        nbytes = int(acc._lib.apr_richardson_lucy_workspace(acc.handle))
+        if self._ws is None or self._ws.numel() < nbytes or self._ws.device != torch.device(device):
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        w, wf = self._stencils[key]
+        return w, wf, self._ws
 
-    def forget(self, acc: G.AprAccess) -> None:
-        self._cache.pop(id(acc), None)
+    def forget(self, acc: Optional[G.AprAccess] = None) -> None:
+        """Release the workspace (it is re-allocated on the next call)."""
+        self._ws = None
 
     def __call__(self, acc: G.AprAccess, u: torch.Tensor, n_iter: int, init: Optional[torch.Tensor] = None,
                  out: Optional[torch.Tensor] = None, power: float = 1.0) -> torch.Tensor:
