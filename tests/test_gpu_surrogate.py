@@ -242,12 +242,6 @@ def test_monitor_and_fallback_paths():
         assert np.isclose(m_ref, np.linalg.norm(r - s) / np.linalg.norm(s), rtol=1e-5)
 
 
-def test_calibrate_tau_rule():
-    assert N.calibrate_tau([0.1, 0.2, 0.3], [0.01, 0.015, 0.03], 0.02) == 0.2
-    assert N.calibrate_tau([0.1, 0.2], [0.03, 0.01], 0.02) == 0.0
-    assert N.calibrate_tau([0.2, 0.2, 0.1], [0.01, 0.03, 0.01], 0.02) == 0.1
-    assert N.calibrate_tau([0.1, 0.3], [0.01, 0.01], 0.02) == 0.3
-
 
 # ---------------------------------------------------------------------------
 # the trained surrogate (weights written by train_surrogate on the GPU)
