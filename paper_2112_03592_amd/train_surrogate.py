@@ -29,9 +29,9 @@ from paper_2112_03592_amd import apr as G  # noqa: E402
 from paper_2112_03592_amd import surrogate as N  # noqa: E402
 
 DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "rl10_surrogate.npz")
-TRAIN_EDGES = (96, 104, 112, 120, 128, 136, 144, 152, 160, 112, 128, 144)
+TRAIN_EDGES = (64, 72, 80, 88, 96, 104, 112, 120, 128, 136, 144, 152, 160, 112, 128, 144)
 TRAIN_SEED = 5000
-CAL_EDGES = (96, 112, 128, 144, 160, 176, 192, 128)
+CAL_EDGES = (72, 88, 96, 112, 128, 144, 160, 176, 192, 128)
 CAL_SEED = 6000
 TARGET = 2e-2
 
@@ -51,7 +51,7 @@ def device_cases(apr_inputs, rl: N.RichardsonLucy, n_iter: int):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--n-pre", type=int, default=3)
     ap.add_argument("--layers", type=int, default=4)
