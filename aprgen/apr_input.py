@@ -231,7 +231,19 @@ CONFIGS = {
     "dense256": SphereConfig((256, 256, 256), 40, 4.0, 24.0, 2, 2001, dense=True),
     # 32^3 sphere field (gradient checks)
     "sphere32": SphereConfig((32, 32, 32), 3, 3.0, 6.0, 1, 4000),
+    # (N_z, N_x, N_y) = 1024 x 2048 x 2048, r in [4, 24], levels 2..11; sphere
+    # counts set for pixels/particles ratios of ~50, ~100 and ~200 (86.6M,
+    # 43.1M and 21.5M particles).  Generated slab by slab, never cached.
+    "field2k_cr50": SphereConfig((1024, 2048, 2048), 3900, 4.0, 24.0, 2, 3000),
+    "field2k_cr100": SphereConfig((1024, 2048, 2048), 1870, 4.0, 24.0, 2, 3000),
+    "field2k_cr200": SphereConfig((1024, 2048, 2048), 890, 4.0, 24.0, 2, 3000),
+    # 1024^3, r in [4, 24], levels 2..10, pixels/particles ~30 (35.8M
+    # particles): the 16-channel layer field.
+    "field1k_layer": SphereConfig((1024, 1024, 1024), 1660, 4.0, 24.0, 2, 4100),
 }
+
+# configurations generated slab by slab (too large to hold their pixel image)
+SLAB_CONFIGS = {"field2k_cr50", "field2k_cr100", "field2k_cr200", "field1k_layer"}
 
 
 def _sphere_params(cfg: SphereConfig):
@@ -293,20 +305,38 @@ def _rule_refined(cfg: SphereConfig, l_max: int, centres, radii) -> Dict[int, np
     return refined
 
 
-def _clean_image(cfg: SphereConfig, centres, radii) -> np.ndarray:
+def _blur_radius(cfg: SphereConfig) -> int:
+    """Rows of context a clean-image row depends on along each axis: the edge
+    blur's support (scipy's radius for truncate=4) plus the PSF's half size."""
+    h = int(4.0 * cfg.edge_sigma + 0.5) if cfg.edge_sigma > 0 else 0
+    if cfg.psf_sigma > 0:
+        h += cfg.psf_size // 2
+    return h
+
+
+def _clean_rows(cfg: SphereConfig, centres, radii, z0: int, z1: int) -> np.ndarray:
+    """Rows ``z0 <= z < z1`` (all x, y) of the clean image.
+
+    The rows are computed on a block widened by the blur radius on both sides
+    (clipped to the image), so each returned row equals the same row of the
+    whole-image computation: zero padding acts only at the image border.
+    """
     from scipy import ndimage
     nz, nx, ny = cfg.dims
-    union = np.zeros(cfg.dims, np.float32)
+    h = _blur_radius(cfg)
+    a0, a1 = max(0, z0 - h), min(nz, z1 + h)
+    union = np.zeros((a1 - a0, nx, ny), np.float32)
     for c, r in zip(centres, radii):
         lo = [max(0, int(np.floor(c[a] - r - 1))) for a in range(3)]
         hi = [min(cfg.dims[a], int(np.ceil(c[a] + r + 1))) for a in range(3)]
-        if any(h <= l for l, h in zip(lo, hi)):
+        lo[0], hi[0] = max(lo[0], a0), min(hi[0], a1)
+        if any(h_ <= l_ for l_, h_ in zip(lo, hi)):
             continue
         zz = (np.arange(lo[0], hi[0]) + 0.5 - c[0]) ** 2
         xx = (np.arange(lo[1], hi[1]) + 0.5 - c[1]) ** 2
         yy = (np.arange(lo[2], hi[2]) + 0.5 - c[2]) ** 2
         inside = (zz[:, None, None] + xx[None, :, None] + yy[None, None, :]) <= r * r
-        view = union[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        view = union[lo[0] - a0:hi[0] - a0, lo[1]:hi[1], lo[2]:hi[2]]
         view[inside] = 1.0
     if cfg.edge_sigma > 0:
         union = ndimage.gaussian_filter(union, cfg.edge_sigma, mode="constant", truncate=4.0)
@@ -319,7 +349,13 @@ def _clean_image(cfg: SphereConfig, centres, radii) -> np.ndarray:
         g /= g.sum()
         for a in range(3):
             img = ndimage.correlate1d(img, g.astype(np.float32), axis=a, mode="constant")
-    return img
+    if a0 == z0 and a1 == z1:
+        return img
+    return np.ascontiguousarray(img[z0 - a0:z1 - a0])
+
+
+def _clean_image(cfg: SphereConfig, centres, radii) -> np.ndarray:
+    return _clean_rows(cfg, centres, radii, 0, cfg.dims[0])
 
 
 def _block_sums(img: np.ndarray, l_max: int, l_min: int):
@@ -382,6 +418,214 @@ def sphere_apr(cfg: SphereConfig, return_image: bool = False):
     return out
 
 
+# ----------------------------------------------------------------------------
+# Slab-wise generation of large sphere fields
+# ----------------------------------------------------------------------------
+
+def _sphere_refined(cfg: SphereConfig, l_max: int, centres, radii) -> Dict[int, np.ndarray]:
+    dims = tuple(int(d) for d in cfg.dims)
+    if cfg.dense:
+        return {l: np.ones(level_dims(dims, l_max, l), bool) for l in range(cfg.l_min, l_max)}
+    return balance_refined(dims, cfg.l_min, l_max, _rule_refined(cfg, l_max, centres, radii))
+
+
+def _leaf_rows(dims, l_min, l_max, l, zl0, zl1, parent, ref):
+    """Leaf mask of level-l rows zl0 <= z < zl1.  ``parent`` holds the
+    level-(l-1) refinement rows zl0//2 .. (zl1+1)//2 (None at l_min), ``ref``
+    the level-l refinement rows zl0..zl1 (None at l_max)."""
+    d = level_dims(dims, l_max, l)
+    if parent is None:
+        exists = np.ones((zl1 - zl0, d[1], d[2]), bool)
+    else:
+        up = parent.repeat(2, 0).repeat(2, 1).repeat(2, 2)
+        off = zl0 - 2 * (zl0 // 2)
+        exists = up[off:off + (zl1 - zl0), :d[1], :d[2]]
+    return exists if ref is None else (exists & ~ref)
+
+
+def _slab_job(args):
+    """One z-slab: clean rows, block sums for the levels whose cells fit in
+    the slab, leaves, Poisson-noisy means.  Returns, per level, the leaves'
+    y (uint16), the per-row counts of the slab's rows (uint64) and the values
+    (float32), plus the block sums of the slab-sized cells."""
+    cfg, l_max, centres, radii, j, slab, l_c, slices = args
+    dims = tuple(int(d) for d in cfg.dims)
+    z0, z1 = j * slab, min(dims[0], (j + 1) * slab)
+    img = _clean_rows(cfg, centres, radii, z0, z1)
+    sums = _block_sums(img, l_max, l_c)
+    del img
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([cfg.seed, 1, j])))
+    out = {}
+    for l in range(max(l_c, cfg.l_min), l_max + 1):
+        s = 1 << (l_max - l)
+        zl0, zl1 = z0 // s, (z1 + s - 1) // s
+        leaf = _leaf_rows(dims, cfg.l_min, l_max, l, zl0, zl1, *slices[l])
+        dz, dx, dy = leaf.shape
+        c = _sorted_cells(leaf)
+        del leaf
+        lam = sums[l][c[:, 0], c[:, 1], c[:, 2]].astype(np.float64)
+        c[:, 0] += zl0
+        cnt = _cell_counts(dims, l_max, l, c)
+        v = rng.poisson(lam) / cnt if cfg.noise else lam / cnt
+        counts = np.bincount((c[:, 0] - zl0).astype(np.int64) * dx + c[:, 1], minlength=dz * dx)
+        out[l] = (c[:, 2].astype(np.uint16), counts.astype(np.uint64), v.astype(np.float32))
+    return j, out, np.asarray(sums[l_c], np.float64)
+
+
+class _AccessCells(dict):
+    """Per-level (z, x, y) cell lists of a LinearAccess, decoded on first use."""
+
+    def __init__(self, dims, l_min, l_max, y_idx, xz_end):
+        super().__init__()
+        self._a = (dims, l_min, l_max, y_idx, xz_end)
+
+    def __missing__(self, l):
+        dims, l_min, l_max, y_idx, xz_end = self._a
+        if not l_min <= l <= l_max:
+            raise KeyError(l)
+        c = _level_cells(dims, l_min, l_max, y_idx, xz_end, l)
+        self[l] = c
+        return c
+
+    def items(self):
+        return [(l, self[l]) for l in range(self._a[1], self._a[2] + 1)]
+
+    def keys(self):
+        return list(range(self._a[1], self._a[2] + 1))
+
+    def __iter__(self):
+        return iter(self.keys())
+
+    def __len__(self):
+        return self._a[2] - self._a[1] + 1
+
+
+def sphere_apr_slabs(cfg: SphereConfig, slab: int = 32, workers: int = 1, progress=None) -> AprInput:
+    """The sphere-field APR generated one z-slab at a time.
+
+    The cell structure is that of ``sphere_apr`` (same rule, same balance).
+    The clean image is only ever held ``slab`` (+ blur radius) rows at a time;
+    each slab's rows equal the whole-image computation, so without noise the
+    values equal ``sphere_apr``'s.  Noise is drawn from one seeded stream per
+    slab (and one for the cells larger than a slab): the same distribution as
+    ``sphere_apr`` (a Poisson draw of each cell's intensity sum), a different
+    realisation.  ``slab`` is a power of two; ``progress(done, total)`` is
+    called as slabs finish.  ``cells`` of the result are decoded lazily.
+    """
+    dims = tuple(int(d) for d in cfg.dims)
+    l_max = lmax_for(dims)
+    if slab & (slab - 1) or slab < 1:
+        raise ValueError("slab must be a power of two")
+    centres, radii = _sphere_params(cfg)
+    refined = _sphere_refined(cfg, l_max, centres, radii)
+    l_c = max(cfg.l_min, l_max - (slab.bit_length() - 1))   # coarsest level done per slab
+    n_slab = (dims[0] + slab - 1) // slab
+    jobs = []
+    for j in range(n_slab):
+        z0, z1 = j * slab, min(dims[0], (j + 1) * slab)
+        sl = {}
+        for l in range(max(l_c, cfg.l_min), l_max + 1):
+            s = 1 << (l_max - l)
+            zl0, zl1 = z0 // s, (z1 + s - 1) // s
+            par = None if l == cfg.l_min else refined[l - 1][zl0 // 2:(zl1 + 1) // 2]
+            ref = refined[l][zl0:zl1] if l < l_max else None
+            sl[l] = (par, ref)
+        jobs.append((cfg, l_max, centres, radii, j, slab, l_c, sl))
+    res = [None] * n_slab
+    if workers <= 1 or n_slab <= 1:
+        for k, jb in enumerate(jobs):
+            j, o, cs = _slab_job(jb)
+            res[j] = (o, cs)
+            if progress:
+                progress(k + 1, n_slab)
+    else:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=min(workers, n_slab), mp_context=mp.get_context("spawn")) as ex:
+            futs = [ex.submit(_slab_job, jb) for jb in jobs]
+            del jobs
+            for k, f in enumerate(cf.as_completed(futs)):
+                j, o, cs = f.result()
+                res[j] = (o, cs)
+                if progress:
+                    progress(k + 1, n_slab)
+    # cells larger than a slab: sums of the slab-sized cells, reduced further
+    coarse = {}
+    if l_c > cfg.l_min:
+        cur = np.concatenate([r[1] for r in res], axis=0)
+        crng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([cfg.seed, 2])))
+        csum = {l_c: cur}
+        for l in range(l_c - 1, cfg.l_min - 1, -1):
+            pads = [(0, d % 2) for d in cur.shape]
+            if any(p[1] for p in pads):
+                cur = np.pad(cur, pads)
+            a, b, c = (d // 2 for d in cur.shape)
+            cur = cur.reshape(a, 2, b, 2, c, 2).sum(axis=(1, 3, 5))
+            csum[l] = cur
+        for l in range(cfg.l_min, l_c):
+            d = level_dims(dims, l_max, l)
+            par = None if l == cfg.l_min else refined[l - 1]
+            leaf = _leaf_rows(dims, cfg.l_min, l_max, l, 0, d[0], par, refined[l])
+            c = _sorted_cells(leaf)
+            lam = csum[l][c[:, 0], c[:, 1], c[:, 2]].astype(np.float64)
+            cnt = _cell_counts(dims, l_max, l, c)
+            v = crng.poisson(lam) / cnt if cfg.noise else lam / cnt
+            counts = np.bincount(c[:, 0].astype(np.int64) * d[1] + c[:, 1], minlength=d[0] * d[1])
+            coarse[l] = (c[:, 2].astype(np.uint16), counts.astype(np.uint64), v.astype(np.float32))
+    del refined
+    ys, cnts, vals = [], [], []
+    for l in range(cfg.l_min, l_max + 1):
+        parts = [coarse[l]] if l in coarse else [r[0][l] for r in res]
+        for y, cn, v in parts:
+            ys.append(y)
+            cnts.append(cn)
+            vals.append(v)
+    del res
+    y_idx = np.concatenate(ys)
+    xz_end = np.cumsum(np.concatenate(cnts), dtype=np.uint64)
+    values = np.concatenate(vals)
+    meta = {"kind": "sphere", "config": dataclasses.asdict(cfg), "l_max": l_max, "slab": slab,
+            "n_particles": int(values.shape[0]), "cr": float(np.prod(dims)) / max(1, values.shape[0])}
+    cells = _AccessCells(dims, cfg.l_min, l_max, y_idx, xz_end)
+    return AprInput(dims, cfg.l_min, l_max, cells, values, y_idx, xz_end, meta)
+
+
+def sphere_level_counts(cfg: SphereConfig) -> Dict[int, int]:
+    """Particles per level of the sphere-field APR (structure only, no image)."""
+    dims = tuple(int(d) for d in cfg.dims)
+    l_max = lmax_for(dims)
+    centres, radii = _sphere_params(cfg)
+    refined = _sphere_refined(cfg, l_max, centres, radii)
+    out = {}
+    for l in range(cfg.l_min, l_max + 1):
+        d = level_dims(dims, l_max, l)
+        n = 0
+        step = max(1, (1 << 26) // max(1, d[1] * d[2]))
+        for z0 in range(0, d[0], step):
+            z1 = min(d[0], z0 + step)
+            par = None if l == cfg.l_min else refined[l - 1][z0 // 2:(z1 + 1) // 2]
+            ref = refined[l][z0:z1] if l < l_max else None
+            n += int(_leaf_rows(dims, cfg.l_min, l_max, l, z0, z1, par, ref).sum())
+        out[l] = n
+    return out
+
+
+def _level_cells(dims, l_min, l_max, y_idx, xz_end, l) -> np.ndarray:
+    ends = np.asarray(xz_end, np.int64)
+    row0 = 0
+    for m in range(l_min, l):
+        dz, dx, _ = level_dims(dims, l_max, m)
+        row0 += dz * dx
+    dz, dx, _ = level_dims(dims, l_max, l)
+    nrow = dz * dx
+    e = ends[row0:row0 + nrow]
+    b = np.concatenate([[ends[row0 - 1] if row0 > 0 else 0], e[:-1]])
+    rows = np.repeat(np.arange(nrow, dtype=np.int64), e - b)
+    p0 = int(ends[row0 - 1]) if row0 > 0 else 0
+    ys = np.asarray(y_idx[p0:p0 + rows.size], np.int32)
+    return np.stack([(rows // dx).astype(np.int32), (rows % dx).astype(np.int32), ys], axis=1)
+
+
 def cells_from_access(dims, l_min, l_max, y_idx, xz_end) -> Dict[int, np.ndarray]:
     """Per-level (z, x, y) cell lists of a LinearAccess (inverse of encode_cells)."""
     cells = {}
@@ -424,6 +668,20 @@ def cached_sphere_apr(name: str, cache_dir: Optional[str] = None) -> AprInput:
     tmp = path + f".{os.getpid()}.tmp.npz"
     np.savez(tmp, values=a.values, y_idx=a.y_idx, xz_end=a.xz_end)
     os.replace(tmp, path)
+    a.meta["name"] = name
+    return a
+
+
+def load_sphere_apr(name: str, workers: Optional[int] = None, progress=None) -> AprInput:
+    """The named configuration: slab-wise generation (uncached, ``workers``
+    processes, default the CPUs available up to 16) for the large fields,
+    ``cached_sphere_apr`` for the rest."""
+    if name not in SLAB_CONFIGS:
+        return cached_sphere_apr(name)
+    import os
+    if workers is None:
+        workers = min(16, len(os.sched_getaffinity(0)))
+    a = sphere_apr_slabs(CONFIGS[name], slab=32, workers=workers, progress=progress)
     a.meta["name"] = name
     return a
 

@@ -101,8 +101,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix peak
 def layers_leg(inp, reps: int = 10):
     """The gather path on the same APR: the network layer shapes (1->16,
     16->16 on MFMA with BF16 activations, 16->16 FP32, 16->1), the 16-channel
-    tree fill, and both gradients of a 16->16 layer (FP32); plus BF16 storage
-    of the single-channel 3^3 / 5^3 convolution against FP32."""
+    tree fill, and both gradients of a 16->16 layer (FP32)."""
     import numpy as np
     import torch
     from aprgen.apr_input import gaussian_stencil
@@ -157,22 +156,42 @@ def layers_leg(inp, reps: int = 10):
     rec["mfma_16to16"] = {"tflops": flops / t / 1e12, "frac_mfma_bf16": flops / t / 1e12 / MFMA_BF16_PEAK_TFLOPS,
                           "GBps": bytes_alg / t / 1e9, "frac_hbm": bytes_alg / t / 1e9 / HBM_PEAK_GBPS,
                           "algorithmic_bytes": bytes_alg}
-    # BF16 storage, single channel
+    acc.close()
+    return rec
+
+
+def bf16_leg(acc, inp, reps: int = 10):
+    """BF16 storage of the single-channel 3^3 / 5^3 convolution (FP32
+    accumulation) against FP32 storage: times and relative L2 difference."""
+    import torch
+    from aprgen.apr_input import gaussian_stencil
+    from paper_2112_03592_amd import apr as G
+
+    def tm(f):
+        f()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
     xs = torch.from_numpy(inp.values).cuda()
     xb = xs.to(torch.bfloat16)
     ts, tb = G.fill_tree(acc, xs), G.fill_tree(acc, xb)
-    prec = {}
+    prec = {"fill_bf16_ms": tm(lambda: G.fill_tree(acc, xb, tb)), "fill_f32_ms": tm(lambda: G.fill_tree(acc, xs, ts))}
     for k in (3, 5):
         w = torch.from_numpy(G.stencil_levels(gaussian_stencil(k, 1.0), "same", k, inp.l_min, inp.l_max)).cuda()
         yf = G.conv(acc, xs, ts, w, k)
         yb = G.conv(acc, xb, tb, w, k, out_dtype=torch.float32)
         d = (yb.double() - yf.double()).norm() / yf.double().norm()
-        prec[f"conv{k}"] = {"bf16_ms": tm(lambda: G.conv(acc, xb, tb, w, k, out_dtype=torch.float32)),
+        prec[f"conv{k}"] = {"bf16_ms": tm(lambda: G.conv(acc, xb, tb, w, k, out_dtype=torch.float32, y=yb)),
                             "f32_ms": tm(lambda: G.conv(acc, xs, ts, w, k, y=yf)),
                             "bf16_vs_f32_rel_l2": float(d)}
-    rec["bf16_single_channel"] = prec
-    acc.close()
-    return rec
+        del yf, yb
+    return prec
 
 
 def surrogate_inputs(which: str):
@@ -271,9 +290,13 @@ def main():
 
     import numpy as np
     import torch
-    from aprgen.apr_input import CONFIGS, cached_sphere_apr
+    from aprgen.apr_input import CONFIGS, load_sphere_apr
     from paper_2112_03592_amd import apr as G
 
+    inp = None
+    if not args.surrogate_only:
+        log(f"workload {args.workload}: generating / loading input")
+        inp = load_sphere_apr(args.workload, progress=lambda d, n: log(f"  slab {d}/{n}") if d % 8 == 0 else None)
     sur_inputs = None
     if args.surrogate_eval != "none" and os.path.exists(args.surrogate_weights):
         sur_inputs = surrogate_inputs(args.surrogate_eval)
@@ -286,8 +309,6 @@ def main():
                          if sur_inputs is not None
                          else {"skipped": "no trained weights or --surrogate-eval none"}), flush=True)
         return
-    log(f"workload {args.workload}: generating / loading input")
-    inp = cached_sphere_apr(args.workload)
     cfg = CONFIGS[args.workload]
     n_p = inp.n_particles
     n_px = int(np.prod(inp.dims))
@@ -372,6 +393,20 @@ def main():
         return {"ms": ms, "Gparticles_s": n_p / (ms * 1e-3) / 1e9,
                 "pixel_equiv_GBps": n_px * 4 / (ms * 1e-3) / 1e9}
 
+    # cold caches: a 1 GiB write between steps evicts L2 and the MALL
+    log("cold-cache steps")
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    n_cold = min(args.steps, 20)
+    cev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n_cold)]
+    for i in range(n_cold):
+        flush.fill_(float(i))
+        step(cev[i])
+    torch.cuda.synchronize()
+    del flush
+    cold = [float(np.mean([e[j].elapsed_time(e[j + 1]) for e in cev])) for j in range(3)]
+    cold_step = sum(cold)
+    alg_frac = {name: kern[name][1] / (kern[name][0] * 1e-3) / 1e9 / HBM_PEAK_GBPS for name in kern}
+
     value = n_p / (ms_per_step * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": "Gparticles/s", "n_gpus": 1, "steps": args.steps,
@@ -388,8 +423,16 @@ def main():
         "pipeline_3x3x3": rate(fill_ms + c3_ms),
         "pipeline_5x5x5": rate(fill_ms + c5_ms),
         "roofline": roof,
+        "hbm_algorithmic_frac": alg_frac,
+        "cold_cache": {"ms_per_step": cold_step, "stages_ms": dict(zip(("fill", "conv3", "conv5"), cold)),
+                       "Gparticles_s": n_p / (cold_step * 1e-3) / 1e9,
+                       "pipeline_3x3x3": rate(cold[0] + cold[1]), "pipeline_5x5x5": rate(cold[0] + cold[2])},
         "source_sha": {k: source_hash(k) for k in KERNEL_SOURCES},
     }
+    log(f"cold caches: step {cold_step:.3f} ms: fill {cold[0]:.3f} conv3 {cold[1]:.3f} conv5 {cold[2]:.3f}")
+    log("BF16 storage, single channel")
+    out["bf16_single_channel"] = bf16_leg(acc, inp)
+    log(f"  {json.dumps(out['bf16_single_channel'])}")
     if not args.no_layers:
         log("layers leg (gather path, 16 channels; BF16 storage)")
         out["layers"] = layers_leg(inp)
