@@ -672,17 +672,40 @@ def cached_sphere_apr(name: str, cache_dir: Optional[str] = None) -> AprInput:
     return a
 
 
-def load_sphere_apr(name: str, workers: Optional[int] = None, progress=None) -> AprInput:
-    """The named configuration: slab-wise generation (uncached, ``workers``
-    processes, default the CPUs available up to 16) for the large fields,
-    ``cached_sphere_apr`` for the rest."""
+def load_sphere_apr(name: str, workers: Optional[int] = None, progress=None,
+                    cache_dir: Optional[str] = None) -> AprInput:
+    """The named configuration: slab-wise generation (``workers`` processes,
+    default the CPUs available up to 16) for the large fields,
+    ``cached_sphere_apr`` for the rest.  A large field is cached only when a
+    cache directory is given (``cache_dir`` or the ``APRGEN_LARGE_CACHE``
+    environment variable): an uncompressed .npz of y_idx, xz_end, values."""
     if name not in SLAB_CONFIGS:
         return cached_sphere_apr(name)
+    import hashlib
     import os
+    cfg = CONFIGS[name]
+    cache_dir = cache_dir or os.environ.get("APRGEN_LARGE_CACHE")
+    path = None
+    if cache_dir:
+        key = hashlib.sha1(repr(dataclasses.astuple(cfg)).encode()).hexdigest()[:10]
+        path = os.path.join(cache_dir, f"{name}_{key}.npz")
+        if os.path.exists(path):
+            z = np.load(path, allow_pickle=False)
+            y_idx, xz_end, values = z["y_idx"], z["xz_end"], z["values"]
+            l_max = lmax_for(cfg.dims)
+            return AprInput(tuple(cfg.dims), cfg.l_min, l_max,
+                            _AccessCells(tuple(cfg.dims), cfg.l_min, l_max, y_idx, xz_end), values, y_idx, xz_end,
+                            meta={"kind": "sphere", "name": name, "n_particles": int(values.shape[0]),
+                                  "cr": float(np.prod(cfg.dims)) / max(1, values.shape[0])})
     if workers is None:
         workers = min(16, len(os.sched_getaffinity(0)))
-    a = sphere_apr_slabs(CONFIGS[name], slab=32, workers=workers, progress=progress)
+    a = sphere_apr_slabs(cfg, slab=32, workers=workers, progress=progress)
     a.meta["name"] = name
+    if path:
+        os.makedirs(cache_dir, exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp.npz"
+        np.savez(tmp, values=a.values, y_idx=a.y_idx, xz_end=a.xz_end)
+        os.replace(tmp, path)
     return a
 
 

@@ -375,8 +375,8 @@ def main():
     if os.path.exists(tpath):
         with open(tpath) as f:
             tj = json.load(f)
-        ent = tj.get("kernels", {}).get(dom)
-        if ent and ent.get("source_sha") == source_hash(dom) and tj.get("workload") == args.workload:
+        ent = tj.get("workloads", {}).get(args.workload, {}).get("kernels", {}).get(dom)
+        if ent and ent.get("source_sha") == source_hash(dom):
             traffic = ent["hbm_bytes_per_launch"]
     if t_hbm >= t_alu:
         achieved = bytes_alg / (t_ms * 1e-3) / 1e9
