@@ -146,6 +146,15 @@ def layers_leg(inp, reps: int = 10):
     ms["fwd_16to16_f32"] = tm(lambda: G.conv(acc, h16, t16, w1616, 3, bias=bias16, relu=True))
     ms["fwd_16to1_bf16_to_f32"] = tm(lambda: G.conv(acc, h16b, t16b, w161, 3, bias=bias1,
                                                      out_dtype=torch.float32))
+    f8 = torch.float8_e4m3fn
+    h16f8 = h16.to(f8)
+    t16f8 = G.fill_tree(acc, h16f8)
+    ms["fill16_fp8"] = tm(lambda: G.fill_tree(acc, h16f8, t16f8))
+    ms["fwd_1to16_f32_to_fp8"] = tm(lambda: G.conv(acc, x1, t1, w11, 3, bias=bias16, relu=True, out_dtype=f8))
+    ms["fwd_16to16_fp8_mfma"] = tm(lambda: G.conv(acc, h16f8, t16f8, w1616, 3, bias=bias16, relu=True))
+    ms["fwd_16to1_fp8_to_f32"] = tm(lambda: G.conv(acc, h16f8, t16f8, w161, 3, bias=bias1,
+                                                    out_dtype=torch.float32))
+    del h16f8, t16f8
     ms["bwd_data_16to16_f32"] = tm(lambda: G.conv_bwd_data(acc, dy, w1616, 3))
     ms["bwd_weight_16to16_f32"] = tm(lambda: G.conv_bwd_weight(acc, h16, t16, dy, 3, nl, 16, 16))
     # MFMA layer against the BF16 matrix peak and the HBM roofline: gathered
@@ -216,9 +225,10 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
     from paper_2112_03592_amd import surrogate as N
     edges = SURROGATE_EVAL[which]
     sur = N.load_surrogate(weights)
+    sur8 = N.load_surrogate(weights, act_dtype=torch.float8_e4m3fn)
     ws = G.Workspace(16)
     rec = {"edges": list(edges), "n_particles": [], "plain_ms": [], "surrogate_ms": [], "error": [],
-           "monitor": [], "fallback": []}
+           "monitor": [], "fallback": [], "fp8": {"surrogate_ms": [], "error": [], "fallback": []}}
     for inp in inputs:
         acc = G.AprAccess.from_input(inp, gather=(3,))
         u = torch.from_numpy(np.maximum(inp.values, 0).astype(np.float32)).cuda()
@@ -243,12 +253,27 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
         rec["error"].append(N.rel_error(res.values, t, ws))
         rec["monitor"].append(res.monitor)
         rec["fallback"].append(bool(res.fallback))
+        # the same network with FP8 (E4M3) hidden activations
+        res8 = sur8(acc, u)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(reps):
+            res8 = sur8(acc, u)
+        torch.cuda.synchronize()
+        rec["fp8"]["surrogate_ms"].append((time.perf_counter() - w0) * 1e3 / reps)
+        rec["fp8"]["error"].append(N.rel_error(res8.values, t, ws))
+        rec["fp8"]["fallback"].append(bool(res8.fallback))
         log(f"  {inp.dims[0]}^3 N_p={inp.n_particles}: plain {plain_ms:.3f} ms, surrogate {sur_ms:.3f} ms, "
-            f"error {rec['error'][-1]:.4f}, monitor {res.monitor:.4f}, fallback {res.fallback}")
+            f"error {rec['error'][-1]:.4f}, monitor {res.monitor:.4f}, fallback {res.fallback}; FP8 activations "
+            f"{rec['fp8']['surrogate_ms'][-1]:.3f} ms, error {rec['fp8']['error'][-1]:.4f}, "
+            f"fallback {res8.fallback}")
         sur.rl.forget(acc)
+        sur8.rl.forget(acc)
         acc.close()
         del t, res, u
     rec["speedup"] = float(np.sum(rec["plain_ms"]) / np.sum(rec["surrogate_ms"]))
+    rec["fp8"]["speedup"] = float(np.sum(rec["plain_ms"]) / np.sum(rec["fp8"]["surrogate_ms"]))
+    rec["fp8"]["max_error"] = float(np.max(rec["fp8"]["error"]))
     rec["max_error"] = float(np.max(rec["error"]))
     rec["tau"] = sur.tau
     rec["start"] = {"iterations": sur.n_pre, "power": sur.power}

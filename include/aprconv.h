@@ -47,6 +47,9 @@ typedef int32_t apr_status;
 /* storage types of particle / tree values */
 #define APR_F32 0
 #define APR_BF16 1
+#define APR_FP8 2   /* FP8 E4M3, OCP "FN" encoding (bias 7, no infinities, NaN 0x7f,
+                       largest finite 448): network activations on the gather path.
+                       Stores round FP32 to nearest even and saturate to +-448. */
 
 /* apr_access_desc.flags */
 #define APR_VALIDATE_PARTITION 1u  /* check on the device that the cells partition the image */
@@ -121,7 +124,8 @@ apr_status apr_access_destroy(apr_handle* h);
  * V is the particle value if c' is a particle and the tree value otherwise;
  * filled from level l_max-1 down to the coarsest tree level.
  * x: device [N_p][channels], tree: device [N_t][channels], both of `dtype`
- * (APR_F32 or APR_BF16; FP32 arithmetic).  Deterministic. Asynchronous. */
+ * (APR_F32, APR_BF16, or APR_FP8 with 16 channels; FP32 arithmetic, each
+ * level's means rounded to the storage type).  Deterministic. Asynchronous. */
 apr_status apr_fill_tree(const apr_handle* h, const void* x, void* tree, int32_t channels,
                          int32_t dtype, void* stream);
 
@@ -155,7 +159,7 @@ typedef struct {
   int32_t k;             /* stencil side: 3 or 5 */
   int32_t c_in, c_out;   /* channels (this build: 1 and 1) */
   int32_t n_wlevels;     /* 1 (one stencil for every level) or l_max-l_min+1 */
-  int32_t x_dtype;       /* APR_F32 / APR_BF16: storage of x and tree */
+  int32_t x_dtype;       /* APR_F32 / APR_BF16 / APR_FP8: storage of x and tree */
   int32_t y_dtype;       /* storage of y */
   int32_t epilogue;      /* APR_EPI_* */
   float eps;             /* clamp of APR_EPI_RATIO */
@@ -183,7 +187,11 @@ apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, 
  * (c_in, c_out): k = 3: (1,1) (1,16) (16,16) (16,1) (2,3); k = 5: (1,1) (2,3).
  * k = 3, 16 -> 16 runs on matrix cores: with BF16 x and tree (8-byte aligned)
  * the weights are rounded to BF16 (FP32 accumulation); with FP32 x and tree
- * (16-byte aligned) FP32 throughout. */
+ * (16-byte aligned) FP32 throughout.  FP8 storage (network activations):
+ * k = 3 only; x FP8 with (16,16) (4-byte aligned x and tree; BF16 weights on
+ * matrix cores, FP8 values widened exactly) or (16,1), y of any type; and
+ * FP32 / BF16 x with (1,16) or (16,16) into FP8 y.  The single-channel
+ * LDS-patch path and the gradients do not take FP8. */
 
 /* Gradient of apr_conv with respect to x (the transpose of the linear map
  * x -> y, bias excluded): same-level taps, taps of level-(l+1) particles that

@@ -11,7 +11,7 @@ from .access import LinearAccess, level_dims, tree_levels
 CHILD_OFFSETS = list(itertools.product((0, 1), repeat=3))
 
 
-def fill_tree(apr: LinearAccess, tree: LinearAccess, x: np.ndarray) -> np.ndarray:
+def fill_tree(apr: LinearAccess, tree: LinearAccess, x: np.ndarray, store=None) -> np.ndarray:
     """Tree values in FP64.
 
     ``x`` is [N_p] or [N_p, C].  For a node c at level L the value is the mean,
@@ -20,6 +20,11 @@ def fill_tree(apr: LinearAccess, tree: LinearAccess, x: np.ndarray) -> np.ndarra
     node (L+1, c').  Section 2.3 and Section 3.4 define coarse values by
     average downsampling; at the image boundary a node may have fewer than
     eight children and the mean runs over the children that exist.
+
+    ``store(sums, counts)``, when given, returns the stored value of each
+    node of a level from its children's sum and count (a storage format:
+    the next coarser level averages the stored values); by default the
+    FP64 mean.
     """
     squeeze = x.ndim == 1
     xv = np.asarray(x, np.float64).reshape(x.shape[0], -1)
@@ -49,5 +54,5 @@ def fill_tree(apr: LinearAccess, tree: LinearAccess, x: np.ndarray) -> np.ndarra
             v[it >= 0] = t[it[it >= 0]]
             acc += v
             cnt += ((ip >= 0) | (it >= 0))
-        t[b:e] = acc / cnt[:, None]
+        t[b:e] = acc / cnt[:, None] if store is None else store(acc, cnt[:, None])
     return t[:, 0] if squeeze else t

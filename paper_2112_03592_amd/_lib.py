@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libaprconv.so")
 APR_OK, APR_EINVAL, APR_EUNBALANCED, APR_EPARTITION, APR_EUNSUPPORTED, APR_ENOMEM, APR_EDEVICE = range(7)
 STATUS_NAMES = {0: "APR_OK", 1: "APR_EINVAL", 2: "APR_EUNBALANCED", 3: "APR_EPARTITION",
                 4: "APR_EUNSUPPORTED", 5: "APR_ENOMEM", 6: "APR_EDEVICE"}
-APR_F32, APR_BF16 = 0, 1
+APR_F32, APR_BF16, APR_FP8 = 0, 1, 2
 APR_VALIDATE_PARTITION, APR_VALIDATE_BALANCE, APR_BUILD_GATHER3, APR_BUILD_GATHER5 = 1, 2, 4, 8
 APR_MAX_LEVELS = 17
 APR_STENCIL_SAME, APR_STENCIL_RESTRICT, APR_STENCIL_ADAPTIVE = 0, 1, 2

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib as L
 
-_DT = {torch.float32: L.APR_F32, torch.bfloat16: L.APR_BF16}
+_DT = {torch.float32: L.APR_F32, torch.bfloat16: L.APR_BF16, torch.float8_e4m3fn: L.APR_FP8}
 _MODES = {"same": L.APR_STENCIL_SAME, "restrict": L.APR_STENCIL_RESTRICT,
           "adaptive": L.APR_STENCIL_ADAPTIVE}
 _EPI = {None: L.APR_EPI_NONE, "ratio": L.APR_EPI_RATIO, "mul": L.APR_EPI_MUL, "mulpow": L.APR_EPI_MULPOW}

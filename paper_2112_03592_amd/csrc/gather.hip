@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "fp8.hpp"
 
 namespace apr {
 
@@ -284,10 +285,20 @@ __device__ inline short bf16_bits(float v) {
 constexpr int kMfmaWaves = 4;
 constexpr int kMfmaBlocksPerXcd = 96;   // 32 CUs x 12 waves / 4 waves per block
 
-template <typename TY>
+// four FP8 codes of a row word widened to the A operand on the conversion
+// unit (exact: every E4M3 value is a BF16 value, so the BF16 bits are the
+// high half of the FP32 bits)
+__device__ inline mfma_s4 fp8x4_to_bf16(uint32_t c) {
+  float f[4];
+  fp8x4_to_f32(c, f);
+  return mfma_s4{short(__float_as_uint(f[0]) >> 16), short(__float_as_uint(f[1]) >> 16),
+                 short(__float_as_uint(f[2]) >> 16), short(__float_as_uint(f[3]) >> 16)};
+}
+
+template <typename TX, typename TY>
 __global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma_kernel(
     const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end,
-    const __hip_bfloat16* __restrict__ x, const __hip_bfloat16* __restrict__ tree, const float* __restrict__ w_level,
+    const TX* __restrict__ x, const TX* __restrict__ tree, const float* __restrict__ w_level,
     const float* __restrict__ bias, int relu, const TY* __restrict__ residual, TY* __restrict__ y) {
   constexpr int K3 = 27;
   // XCD blockIdx % 8 takes the contiguous tile range [tb, te); its waves
@@ -314,17 +325,30 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma_kernel(
     uint32_t g[K3];
 #pragma unroll
     for (int q = 0; q < K3; ++q) g[q] = valid ? gmap[size_t(q) * size_t(n_p) + p] : kPad;
-    mfma_s4 a[K3];
-#pragma unroll
-    for (int q = 0; q < K3; ++q) {
-      a[q] = mfma_s4{0, 0, 0, 0};
-      if (g[q] != kPad)
-        a[q] = *reinterpret_cast<const mfma_s4*>(((g[q] >> 30) == 3 ? tree : x) + size_t(g[q] & kIdxMask) * 16 +
-                                                 4 * kg);
-    }
     mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (std::is_same<TX, fp8e4m3>::value) {
+      // every row word in flight first, then widen and multiply tap by tap
+      uint32_t raw[K3];
 #pragma unroll
-    for (int q = 0; q < K3; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], bw[q], acc, 0, 0, 0);
+      for (int q = 0; q < K3; ++q)
+        raw[q] = (g[q] != kPad) ? *reinterpret_cast<const uint32_t*>(((g[q] >> 30) == 3 ? tree : x) +
+                                                                     size_t(g[q] & kIdxMask) * 16 + 4 * kg)
+                                : 0u;
+#pragma unroll
+      for (int q = 0; q < K3; ++q)
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fp8x4_to_bf16(raw[q]), bw[q], acc, 0, 0, 0);
+    } else {
+      mfma_s4 a[K3];
+#pragma unroll
+      for (int q = 0; q < K3; ++q) {
+        a[q] = mfma_s4{0, 0, 0, 0};
+        if (g[q] != kPad)
+          a[q] = *reinterpret_cast<const mfma_s4*>(((g[q] >> 30) == 3 ? tree : x) + size_t(g[q] & kIdxMask) * 16 +
+                                                   4 * kg);
+      }
+#pragma unroll
+      for (int q = 0; q < K3; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], bw[q], acc, 0, 0, 0);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t pm = t0 + 4 * kg + i;
@@ -337,7 +361,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma_kernel(
   }
 }
 
-template <typename TY>
+template <typename TX, typename TY>
 static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                              const float* w, void* y, hipStream_t s) {
   const Meta& m = h->meta;
@@ -349,10 +373,10 @@ static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const 
       const uint32_t tiles = (np_l + 15) / 16;
       // enough waves to fill every CU (3 per SIMD), no more than one per tile
       const uint32_t blocks_per_xcd = std::min<uint32_t>(kMfmaBlocksPerXcd, (tiles / 8 + kMfmaWaves) / kMfmaWaves);
-      hipLaunchKernelGGL((mc16_mfma_kernel<TY>), dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)),
+      hipLaunchKernelGGL((mc16_mfma_kernel<TX, TY>), dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)),
                          dim3(64 * kMfmaWaves), 0, s, reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p,
-                         begin, begin + np_l, static_cast<const __hip_bfloat16*>(x),
-                         static_cast<const __hip_bfloat16*>(tree), wl, d->bias, d->relu,
+                         begin, begin + np_l, static_cast<const TX*>(x), static_cast<const TX*>(tree), wl, d->bias,
+                         d->relu,
                          static_cast<const TY*>(d->residual), static_cast<TY*>(y));
     }
     begin += np_l;
@@ -482,18 +506,65 @@ static apr_status mc_fwd_dtypes(const apr_handle* h, const apr_conv_desc* d, con
   return APR_OK;
 }
 
+// FP8 activations (network shapes, k = 3): FP8 x into 16 -> 16 on matrix
+// cores or 16 -> 1 on the vector ALUs; FP32 / BF16 x into FP8 y.
+template <typename TY>
+static apr_status mc_fp8_in(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                            const float* w, void* y, hipStream_t s) {
+  if (d->c_in == 16 && d->c_out == 16) {
+    if (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 3) != 0)
+      APR_FAIL(APR_EINVAL, "apr_conv: FP8 rows must be 4-byte aligned");
+    launch_mc16_mfma<fp8e4m3, TY>(h, d, x, tree, w, y, s);
+  } else {
+    launch_mc_fwd<3, 16, 1, fp8e4m3, TY>(h, d, x, tree, w, y, s);
+  }
+  APR_HIP(hipGetLastError());
+  return APR_OK;
+}
+
+template <typename TX>
+static apr_status mc_fp8_out(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                             const float* w, void* y, hipStream_t s) {
+  if (d->c_in == 1)
+    launch_mc_fwd<3, 1, 16, TX, fp8e4m3>(h, d, x, tree, w, y, s);
+  else
+    launch_mc_fwd<3, 16, 16, TX, fp8e4m3>(h, d, x, tree, w, y, s);
+  APR_HIP(hipGetLastError());
+  return APR_OK;
+}
+
+static apr_status mc_conv_fp8(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
+                              const float* w, void* y, hipStream_t s) {
+  const int cin = d->c_in, cout = d->c_out;
+  if (d->k != 3) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: FP8 storage needs k = 3");
+  if (d->x_dtype == APR_FP8) {
+    if (!((cin == 16 && cout == 16) || (cin == 16 && cout == 1)))
+      APR_FAIL(APR_EUNSUPPORTED, "apr_conv: FP8 x supports (c_in, c_out) = (16,16) and (16,1)");
+    if (d->y_dtype == APR_FP8) return mc_fp8_in<fp8e4m3>(h, d, x, tree, w, y, s);
+    if (d->y_dtype == APR_BF16) return mc_fp8_in<__hip_bfloat16>(h, d, x, tree, w, y, s);
+    if (d->y_dtype == APR_F32) return mc_fp8_in<float>(h, d, x, tree, w, y, s);
+    APR_FAIL(APR_EUNSUPPORTED, "apr_conv: unsupported dtype combination");
+  }
+  if (!((cin == 1 && cout == 16) || (cin == 16 && cout == 16)))
+    APR_FAIL(APR_EUNSUPPORTED, "apr_conv: FP8 y supports (c_in, c_out) = (1,16) and (16,16)");
+  if (d->x_dtype == APR_F32) return mc_fp8_out<float>(h, d, x, tree, w, y, s);
+  if (d->x_dtype == APR_BF16) return mc_fp8_out<__hip_bfloat16>(h, d, x, tree, w, y, s);
+  APR_FAIL(APR_EUNSUPPORTED, "apr_conv: unsupported dtype combination");
+}
+
 apr_status mc_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                    const float* w, void* y, hipStream_t s) {
   if (!gather_map(h, d->k))
     APR_FAIL(APR_EINVAL, "apr_conv: this path needs the gather map; build the access with "
                          "APR_BUILD_GATHER3 / APR_BUILD_GATHER5");
   const int cin = d->c_in, cout = d->c_out;
+  if (d->x_dtype == APR_FP8 || d->y_dtype == APR_FP8) return mc_conv_fp8(h, d, x, tree, w, y, s);
   if (d->k == 3 && cin == 16 && cout == 16 && d->x_dtype == APR_BF16 &&
       ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 7) == 0) {
     if (d->y_dtype == APR_BF16)
-      launch_mc16_mfma<__hip_bfloat16>(h, d, x, tree, w, y, s);
+      launch_mc16_mfma<__hip_bfloat16, __hip_bfloat16>(h, d, x, tree, w, y, s);
     else
-      launch_mc16_mfma<float>(h, d, x, tree, w, y, s);
+      launch_mc16_mfma<__hip_bfloat16, float>(h, d, x, tree, w, y, s);
     APR_HIP(hipGetLastError());
     return APR_OK;
   }

@@ -12,6 +12,7 @@
 // map).  The coarse levels, which hold few nodes, are filled by one
 // workgroup in a single launch.
 #include "common.hpp"
+#include "fp8.hpp"
 
 namespace apr {
 
@@ -260,10 +261,17 @@ extern "C" apr_status apr_fill_tree(const apr_handle* h, const void* x, void* tr
                                     int32_t channels, int32_t dtype, void* stream) {
   if (!h) APR_FAIL(APR_EINVAL, "apr_fill_tree: null handle");
   if (channels < 1 || channels > 65535) APR_FAIL(APR_EINVAL, "apr_fill_tree: channels must be in [1, 65535]");
-  if (dtype != APR_F32 && dtype != APR_BF16) APR_FAIL(APR_EUNSUPPORTED, "apr_fill_tree: dtype");
+  if (dtype != APR_F32 && dtype != APR_BF16 && dtype != APR_FP8) APR_FAIL(APR_EUNSUPPORTED, "apr_fill_tree: dtype");
+  if (dtype == APR_FP8 && (channels != 16 || !h->cmap))
+    APR_FAIL(APR_EUNSUPPORTED, "apr_fill_tree: FP8 storage needs 16 channels (and the child map)");
   if (h->n_t == 0) return APR_OK;
   if (!x || !tree) APR_FAIL(APR_EINVAL, "apr_fill_tree: null x or tree");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == APR_FP8) {
+    if (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 15) != 0)
+      APR_FAIL(APR_EINVAL, "apr_fill_tree: FP8 rows must be 16-byte aligned");
+    return fill_by_child_map<fp8e4m3, 16>(h, static_cast<const fp8e4m3*>(x), static_cast<fp8e4m3*>(tree), 16, s);
+  }
   if (h->cmap)
     return dtype == APR_F32 ? fill_dispatch<float>(h, x, tree, channels, s)
                             : fill_dispatch<__hip_bfloat16>(h, x, tree, channels, s);
