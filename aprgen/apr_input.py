@@ -717,6 +717,17 @@ def gaussian_stencil(k: int, sigma: float) -> np.ndarray:
     return np.einsum("i,j,k->ijk", g, g, g)
 
 
+def sobel_stencils() -> np.ndarray:
+    """The three 3^3 Sobel filters [3, 3, 3, 3] (d/dz, d/dx, d/dy), a filter
+    input: a central difference along one axis times [1, 2, 1] smoothing along
+    the other two, scaled by 1/32 so that a unit-slope ramp on pixels gives 1."""
+    d = np.array([-1.0, 0.0, 1.0])
+    sm = np.array([1.0, 2.0, 1.0])
+    out = np.stack([np.einsum("i,j,k->ijk", d, sm, sm), np.einsum("i,j,k->ijk", sm, d, sm),
+                    np.einsum("i,j,k->ijk", sm, sm, d)])
+    return out / 32.0
+
+
 # ----------------------------------------------------------------------------
 # Deconvolution workload: sphere fields blurred by a 5^3 Gaussian PSF
 # (sigma 1.5) and corrupted by Poisson noise.  Sphere count scales with the

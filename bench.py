@@ -203,6 +203,33 @@ def bf16_leg(acc, inp, reps: int = 10):
     return prec
 
 
+def gradmag_leg(acc, inp, x, tree, reps: int = 20):
+    """Resolution-adaptive gradient magnitude: three level-scaled 3^3 Sobel
+    stencils on one patch, |grad| written per particle (after a tree fill)."""
+    import numpy as np
+    import torch
+    from aprgen.apr_input import sobel_stencils
+    from paper_2112_03592_amd import apr as G
+    w3 = torch.from_numpy(G.stencil_levels(sobel_stencils(), "adaptive", 3, inp.l_min, inp.l_max)).cuda()
+    y = torch.empty(inp.n_particles, dtype=torch.float32, device="cuda")
+    G.fill_tree(acc, x, tree)
+    G.gradient_magnitude(acc, x, tree, w3, y)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        G.fill_tree(acc, x, tree)
+    e[1].record()
+    for _ in range(reps):
+        G.gradient_magnitude(acc, x, tree, w3, y)
+    e[2].record()
+    torch.cuda.synchronize()
+    fill_ms, g_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    n_p = inp.n_particles
+    return {"ms": g_ms, "fill_ms": fill_ms, "Gparticles_s": n_p / ((fill_ms + g_ms) * 1e-3) / 1e9,
+            "pixel_equiv_GBps": float(np.prod(inp.dims)) * 4 / ((fill_ms + g_ms) * 1e-3) / 1e9}
+
+
 def surrogate_inputs(which: str):
     """The batch's APRs, generated in worker processes (before this process
     touches the GPU)."""
@@ -457,6 +484,8 @@ def main():
     log(f"cold caches: step {cold_step:.3f} ms: fill {cold[0]:.3f} conv3 {cold[1]:.3f} conv5 {cold[2]:.3f}")
     log("BF16 storage, single channel")
     out["bf16_single_channel"] = bf16_leg(acc, inp)
+    out["gradient_magnitude"] = gradmag_leg(acc, inp, x, tree)
+    log(f"  gradient magnitude: {json.dumps(out['gradient_magnitude'])}")
     log(f"  {json.dumps(out['bf16_single_channel'])}")
     if not args.no_layers:
         log("layers leg (gather path, 16 channels; BF16 storage)")

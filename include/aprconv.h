@@ -154,6 +154,10 @@ apr_status apr_stencil_levels(int32_t mode, int32_t k, int32_t n_filters, const 
 #define APR_EPI_RATIO 1   /* y = u / max(y, eps)   (Richardson-Lucy quotient, Section 6.2) */
 #define APR_EPI_MUL 2     /* y = y * u             (Richardson-Lucy update) */
 #define APR_EPI_MULPOW 3  /* y = u * max(y, 0)^power (update raised to a power; power 1 is MUL) */
+#define APR_EPI_GRADMAG 4 /* three stencils per level, y = sqrt(sum_j (w_j * V)^2): the magnitude of a
+                             gradient filter (Section 4.3, Eq. adapt_grad, with per-level stencils
+                             2^-(l_max-l) w from APR_STENCIL_ADAPTIVE); k = 3, c_in = c_out = 1,
+                             w is [n_wlevels][3][k^3], x F32 or BF16, y F32 */
 
 typedef struct {
   int32_t k;             /* stencil side: 3 or 5 */

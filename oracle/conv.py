@@ -289,3 +289,24 @@ def abs_scale(apr: LinearAccess, x, w, tree=None) -> np.ndarray:
     """M_p = sum_o |W_l[o]| |V_l(c_p+o)| bounded above by the convolution of
     |x| with |W| (tree values of |x| dominate |tree values of x|)."""
     return apr_conv(apr, np.abs(np.asarray(x, np.float64)), np.abs(np.asarray(w, np.float64)), tree=tree)
+
+
+def gradient_magnitude(apr: LinearAccess, x, w3, tree: Optional[LinearAccess] = None,
+                       sample: Optional[np.ndarray] = None) -> np.ndarray:
+    """|grad| from three stencils per level (Section 4.3, Eq. adapt_grad, with
+    the per-level stencils w3 [n_levels or 1, 3, k, k, k]): the square root of
+    the sum of the squares of the three APR convolutions; at the particles
+    ``sample`` by keyed lookup when given."""
+    w3 = np.asarray(w3, np.float64)
+    tree = tree_structure(apr) if tree is None else tree
+    x1 = np.asarray(x, np.float64).reshape(-1)
+    tv = fill_tree(apr, tree, x1)
+    sq = 0.0
+    for j in range(3):
+        wj = w3[:, j]
+        if sample is None:
+            g = apr_conv(apr, x1, wj, tree=tree, tvals=tv)
+        else:
+            g = apr_conv_keyed(apr, x1, wj, sample, tree=tree, tvals=tv)[:, 0]
+        sq = sq + np.asarray(g).reshape(-1) ** 2
+    return np.sqrt(sq)

@@ -18,7 +18,7 @@ APR_F32, APR_BF16, APR_FP8 = 0, 1, 2
 APR_VALIDATE_PARTITION, APR_VALIDATE_BALANCE, APR_BUILD_GATHER3, APR_BUILD_GATHER5 = 1, 2, 4, 8
 APR_MAX_LEVELS = 17
 APR_STENCIL_SAME, APR_STENCIL_RESTRICT, APR_STENCIL_ADAPTIVE = 0, 1, 2
-APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL, APR_EPI_MULPOW = 0, 1, 2, 3
+APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL, APR_EPI_MULPOW, APR_EPI_GRADMAG = 0, 1, 2, 3, 4
 
 EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree", "apr_access_destroy",
             "apr_fill_tree", "apr_stencil_levels", "apr_conv", "apr_neighbor_map",

@@ -17,7 +17,8 @@ from . import _lib as L
 _DT = {torch.float32: L.APR_F32, torch.bfloat16: L.APR_BF16, torch.float8_e4m3fn: L.APR_FP8}
 _MODES = {"same": L.APR_STENCIL_SAME, "restrict": L.APR_STENCIL_RESTRICT,
           "adaptive": L.APR_STENCIL_ADAPTIVE}
-_EPI = {None: L.APR_EPI_NONE, "ratio": L.APR_EPI_RATIO, "mul": L.APR_EPI_MUL, "mulpow": L.APR_EPI_MULPOW}
+_EPI = {None: L.APR_EPI_NONE, "ratio": L.APR_EPI_RATIO, "mul": L.APR_EPI_MUL, "mulpow": L.APR_EPI_MULPOW,
+        "gradmag": L.APR_EPI_GRADMAG}
 
 
 def _stream() -> int:
@@ -184,6 +185,27 @@ def conv(acc: AprAccess, x: torch.Tensor, tree: torch.Tensor, w: torch.Tensor, k
     L.check(acc._lib.apr_conv(acc.handle, ctypes.byref(d), _ptr(x),
                               _ptr(tree) if tree is not None and tree.numel() else None,
                               _ptr(w), _ptr(y), _stream()))
+    return y
+
+
+def gradient_magnitude(acc: AprAccess, x: torch.Tensor, tree: torch.Tensor, w3: torch.Tensor,
+                       y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """|grad| of particle values x [N_p] (FP32 or BF16) from three 3^3 stencils
+    per level, w3 FP32 [nw, 3, 3, 3, 3] (``apr_conv`` with APR_EPI_GRADMAG);
+    per-level stencils come from ``stencil_levels(..., "adaptive", ...)``."""
+    if w3.dtype != torch.float32 or w3.dim() != 5 or tuple(w3.shape[1:]) != (3, 3, 3, 3):
+        raise ValueError("w3 must be FP32 [nw, 3, 3, 3, 3]")
+    nw = w3.shape[0]
+    if nw not in (1, acc.n_levels):
+        raise ValueError("w3 must hold 1 or n_levels stencil triples")
+    if x.dim() != 1 or x.shape[0] != acc.n_particles:
+        raise ValueError("x has the wrong shape")
+    if y is None:
+        y = torch.empty(acc.n_particles, dtype=torch.float32, device=x.device)
+    d = _desc(3, 1, 1, nw, x.dtype, y.dtype, "gradmag")
+    L.check(acc._lib.apr_conv(acc.handle, ctypes.byref(d), _ptr(x),
+                              _ptr(tree) if tree is not None and tree.numel() else None,
+                              _ptr(w3.contiguous()), _ptr(y), _stream()))
     return y
 
 

@@ -106,7 +106,9 @@ __device__ inline int find_row(const uint32_t* pre, int n, uint32_t v) {
   return lo;
 }
 
-template <int K, typename TX, typename TY, bool INDEX>
+// NF = 3: three stencils per level on the same patch (the three directions of
+// a gradient filter), output the magnitude sqrt(sum of squares).
+template <int K, typename TX, typename TY, bool INDEX, int NF = 1>
 __global__ __launch_bounds__(ConvShape<K>::kThreads)
 __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
   constexpr int NT = ConvShape<K>::kThreads, NW = NT / 64;
@@ -167,7 +169,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
   // per-level weights: read-only for the whole launch and uniform across the
   // workgroup, so the tap loop reads them through scalar loads
   using cfloat = const __attribute__((address_space(4))) float;
-  cfloat* wl = (cfloat*)(uintptr_t)(INDEX ? a.w : a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * K3);
+  cfloat* wl = (cfloat*)(uintptr_t)(INDEX ? a.w : a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * K3 * NF);
 
   // ---- setup
   const PT pad = INDEX ? PT(-1) : PT(0);
@@ -426,6 +428,24 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
               for (int dy = 0; dy < K; ++dy)
                 dst[q++] = int64_t(patch[((hz + dz) * HX + hx + dx) * PY + p0 - R + dy]);
         }
+      } else if constexpr (NF == 3) {
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll 1
+        for (int dz = 0; dz < K; ++dz) {
+          cfloat* wz = wl + dz * K * K;
+#pragma unroll
+          for (int dx = 0; dx < K; ++dx) {
+            const float* row = &patch[((hz + dz) * HX + hx + dx) * PY + p0 - R];
+#pragma unroll
+            for (int dy = 0; dy < K; ++dy) {
+              const float v = row[dy];
+              g0 = fmaf(wz[dx * K + dy], v, g0);
+              g1 = fmaf(wz[K3 + dx * K + dy], v, g1);
+              g2 = fmaf(wz[2 * K3 + dx * K + dy], v, g2);
+            }
+          }
+        }
+        static_cast<TY*>(a.y)[idx] = from_f32<TY>(sqrtf(fmaf(g0, g0, fmaf(g1, g1, g2 * g2))));
       } else {
         float acc = 0.f;
 #pragma unroll 1
@@ -459,6 +479,18 @@ template <int K, bool INDEX>
 static apr_status launch_conv(const ConvArgs& args, int xdt, int ydt, hipStream_t s) {
   const int64_t per = (args.n_tiles + 7) / 8;
   const dim3 grid(unsigned(per * 8));
+  if (!INDEX && args.epi == APR_EPI_GRADMAG) {
+    if (K != 3) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: APR_EPI_GRADMAG needs k = 3");
+    if (xdt == APR_F32 && ydt == APR_F32)
+      hipLaunchKernelGGL((conv1_kernel<3, float, float, false, 3>), grid, dim3(ConvShape<3>::kThreads), 0, s, args);
+    else if (xdt == APR_BF16 && ydt == APR_F32)
+      hipLaunchKernelGGL((conv1_kernel<3, __hip_bfloat16, float, false, 3>), grid, dim3(ConvShape<3>::kThreads), 0, s,
+                         args);
+    else
+      APR_FAIL(APR_EUNSUPPORTED, "apr_conv: APR_EPI_GRADMAG takes F32 or BF16 x and F32 y");
+    APR_HIP(hipGetLastError());
+    return APR_OK;
+  }
   if (xdt == APR_F32 && ydt == APR_F32)
     hipLaunchKernelGGL((conv1_kernel<K, float, float, INDEX>), grid, dim3(ConvShape<K>::kThreads), 0, s, args);
   else if (xdt == APR_BF16 && ydt == APR_BF16)
@@ -510,11 +542,12 @@ apr_status apr::conv_impl(const apr_handle* h, const apr_conv_desc* d, const voi
   const int nl = h->meta.l_max - h->meta.l_min + 1;
   if (d->n_wlevels != 1 && d->n_wlevels != nl)
     APR_FAIL(APR_EINVAL, "apr_conv: n_wlevels must be 1 or l_max - l_min + 1");
-  if (d->epilogue < APR_EPI_NONE || d->epilogue > APR_EPI_MULPOW)
+  if (d->epilogue < APR_EPI_NONE || d->epilogue > APR_EPI_GRADMAG)
     APR_FAIL(APR_EINVAL, "apr_conv: unknown epilogue");
   if (h->n_p == 0 || h->n_tiles == 0) return APR_OK;
   if (!x || !w || !y || (h->n_t && !tree)) APR_FAIL(APR_EINVAL, "apr_conv: null buffer");
-  if (d->epilogue != APR_EPI_NONE && !d->epi_arg) APR_FAIL(APR_EINVAL, "apr_conv: null epi_arg");
+  if (d->epilogue != APR_EPI_NONE && d->epilogue != APR_EPI_GRADMAG && !d->epi_arg)
+    APR_FAIL(APR_EINVAL, "apr_conv: null epi_arg");
   if (y == x || y == tree) APR_FAIL(APR_EINVAL, "apr_conv: y must not alias x or tree");
   if (d->c_in != 1 || d->c_out != 1 || d->bias || d->relu || d->residual) {
     if (d->epilogue != APR_EPI_NONE) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: epilogues need c_in = c_out = 1");
