@@ -29,7 +29,7 @@ FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
 KERNEL_SOURCES = {"conv3": ["conv.hip", "common.hpp"], "conv5": ["conv.hip", "common.hpp"],
-                  "fill": ["tree.hip", "common.hpp"]}
+                  "fill": ["tree.hip", "common.hpp"], "gradmag": ["conv.hip", "common.hpp"]}
 
 
 def source_hash(kernel: str = "conv5") -> str:

@@ -185,7 +185,7 @@ typedef struct {
 apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                     const float* w, void* y, void* stream);
 /* Paths: c_in = c_out = 1 without bias / relu / residual runs the LDS-patch
- * kernels; every other request (multichannel Y[p,co] = b[co] + sum_{ci,o}
+ * kernels (so does APR_EPI_GRADMAG, three stencils on one patch); every other request (multichannel Y[p,co] = b[co] + sum_{ci,o}
  * W_l[co][ci][o] V_l[ci](c_p + o)) runs on the gather map and needs the handle
  * built with APR_BUILD_GATHER3 / APR_BUILD_GATHER5 for d->k.  Supported
  * (c_in, c_out): k = 3: (1,1) (1,16) (16,16) (16,1) (2,3); k = 5: (1,1) (2,3).
