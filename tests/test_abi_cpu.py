@@ -100,3 +100,15 @@ def test_build_rejects_malformed_arrays_on_the_host():
     # last row end must equal the particle count
     st, _ = _build_raw(inp.dims, inp.l_min, inp.l_max, inp.y_idx[:-1], e)
     assert st == L.APR_EINVAL
+
+
+def test_binding_constants_match_the_header():
+    """Every #define APR_* the binding names has the header's value."""
+    txt = open(HEADER).read()
+    defined = {m.group(1): int(m.group(2), 0)
+               for m in re.finditer(r"^#define\s+(APR_\w+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", txt, re.M)}
+    names = [n for n in dir(L) if n.startswith("APR_") and isinstance(getattr(L, n), int)]
+    assert {"APR_F32", "APR_BF16", "APR_FP8", "APR_EPI_GRADMAG", "APR_EPI_MULPOW"} <= set(names)
+    for n in names:
+        if n in defined:
+            assert getattr(L, n) == defined[n], n
