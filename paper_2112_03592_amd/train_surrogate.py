@@ -29,9 +29,9 @@ from paper_2112_03592_amd import apr as G  # noqa: E402
 from paper_2112_03592_amd import surrogate as N  # noqa: E402
 
 DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "rl10_surrogate.npz")
-TRAIN_EDGES = (64, 72, 80, 88, 96, 104, 112, 120, 128, 136, 144, 152, 160, 112, 128, 144)
+TRAIN_EDGES = (64, 80, 96, 112, 128, 144, 160, 176, 192, 208, 224, 240, 256, 112, 160, 208)
 TRAIN_SEED = 5000
-CAL_EDGES = (72, 88, 96, 112, 128, 144, 160, 176, 192, 128)
+CAL_EDGES = (72, 96, 112, 128, 160, 192, 224, 256, 288, 128)
 CAL_SEED = 6000
 TARGET = 2e-2
 
@@ -51,20 +51,24 @@ def device_cases(apr_inputs, rl: N.RichardsonLucy, n_iter: int):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--n-pre", type=int, default=3)
+    ap.add_argument("--n-pre", type=int, default=2)
     ap.add_argument("--layers", type=int, default=4)
     ap.add_argument("--channels", type=int, default=16)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--train-edges", default=",".join(map(str, TRAIN_EDGES)), help="edges of the training APRs")
+    ap.add_argument("--cal-edges", default=",".join(map(str, CAL_EDGES)), help="edges of the held-out APRs")
     a = ap.parse_args(argv)
     t0 = time.time()
     psf = deconv_psf()
     # generated in worker processes before this process touches the GPU
-    train_in = deconv_set(TRAIN_EDGES, TRAIN_SEED, a.workers)
-    cal_in = deconv_set(CAL_EDGES, CAL_SEED, a.workers)
+    train_edges = tuple(int(e) for e in a.train_edges.split(","))
+    cal_edges = tuple(int(e) for e in a.cal_edges.split(","))
+    train_in = deconv_set(train_edges, TRAIN_SEED, a.workers)
+    cal_in = deconv_set(cal_edges, CAL_SEED, a.workers)
     rl = N.RichardsonLucy(psf)
     ws = G.Workspace(16)
     say(f"generated {len(train_in)} + {len(cal_in)} APRs in {time.time() - t0:.1f} s; particles "
@@ -91,7 +95,7 @@ def main(argv=None):
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     N.save_surrogate(a.out, sur, train_loss=np.asarray(losses), cal_monitor=np.asarray(mon),
                      cal_error=np.asarray(err), cal_base_error=np.asarray(base_err),
-                     train_edges=np.asarray(TRAIN_EDGES), cal_edges=np.asarray(CAL_EDGES),
+                     train_edges=np.asarray(train_edges), cal_edges=np.asarray(cal_edges),
                      steps=np.array(a.steps), lr=np.array(a.lr))
     say(f"wrote {a.out} ({time.time() - t0:.1f} s)")
     for acc, _, _ in train + cal:
