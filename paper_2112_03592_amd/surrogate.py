@@ -322,10 +322,11 @@ def calibrate_power(rl: RichardsonLucy, cases, n_pre: int, ws: G.Workspace,
 
 
 def train(net: SurrogateNet, cases, steps: int, lr: float = 1e-3, lr_min: float = 1e-5,
-          log_every: int = 0) -> List[float]:
+          log_every: int = 0, progress=None) -> List[float]:
     """Adam over the training cases (acc, base, target) in turn, cosine
     learning-rate decay from lr to lr_min.  Returns the per-step losses
-    |s - t| / |t| (read back every ``log_every`` steps; empty when 0)."""
+    |s - t| / |t| (read back every ``log_every`` steps; empty when 0);
+    ``progress(step, loss)`` is called at each read-back."""
     losses: List[float] = []
     for it in range(steps):
         acc, b, t = cases[it % len(cases)]
@@ -333,6 +334,8 @@ def train(net: SurrogateNet, cases, steps: int, lr: float = 1e-3, lr_min: float 
         out = net.train_step(acc, b, t, rate)
         if log_every and (it % log_every == 0 or it == steps - 1):
             losses.append(float(np.sqrt(max(float(out[0].item()), 0.0))))
+            if progress:
+                progress(it, losses[-1])
     return losses
 
 

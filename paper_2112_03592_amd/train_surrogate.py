@@ -81,7 +81,8 @@ def main(argv=None):
     net = N.SurrogateNet(N.NetConfig(channels=a.channels, layers=a.layers, seed=a.seed))
     cases = [(acc, rl(acc, u, a.n_pre, power=power), t) for acc, u, t in train]
     t1 = time.time()
-    losses = N.train(net, cases, a.steps, lr=a.lr, log_every=max(1, a.steps // 20))
+    losses = N.train(net, cases, a.steps, lr=a.lr, log_every=max(1, a.steps // 20),
+                     progress=lambda it, loss: say(f"  step {it}: loss {loss:.4f}"))
     torch.cuda.synchronize()
     say(f"trained {a.steps} steps in {time.time() - t1:.1f} s; loss {np.round(losses, 4).tolist()}")
     sur = N.RLSurrogate(net, psf, 10, a.n_pre, power)

@@ -266,7 +266,7 @@ def test_trained_surrogate_against_fp64_oracle_rl10(edge, seed):
     u = np.maximum(inp.values, 0).astype(np.float32)
     t = oracle_rl(la, u.astype(np.float64), psf, 10)
     sur = N.load_surrogate(TRAINED)
-    fresh = N.RLSurrogate(N.SurrogateNet(N.NetConfig(seed=7)), psf, 10, sur.n_pre, sur.power)
+    fresh = N.RLSurrogate(N.SurrogateNet(N.NetConfig(layers=sur.net.cfg.layers, seed=7)), psf, 10, sur.n_pre, sur.power)
     with G.AprAccess.from_input(inp, gather=(3,)) as acc:
         ud = dev(u)
         est, mon = sur.estimate(acc, ud)
