@@ -510,6 +510,18 @@ def main():
     torch.cuda.synchronize()
     del flush
     cold = [float(np.mean([e[j].elapsed_time(e[j + 1]) for e in cev])) for j in range(3)]
+    # the device's own copy bandwidth (read + write of 1 GiB), for scale
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * src.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
     cold_step = sum(cold)
     alg_frac = {name: kern[name][1] / (kern[name][0] * 1e-3) / 1e9 / HBM_PEAK_GBPS for name in kern}
 
@@ -530,6 +542,10 @@ def main():
         "pipeline_5x5x5": rate(fill_ms + c5_ms),
         "roofline": roof,
         "hbm_algorithmic_frac": alg_frac,
+        "hbm_fractions_dominant": {"kernel": dom, "algorithmic": bytes_alg / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                   "measured_traffic": (None if traffic is None
+                                                        else traffic / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS),
+                                   "copy_kernel": copy_gbps / HBM_PEAK_GBPS, "copy_GBps": copy_gbps},
         "cold_cache": {"ms_per_step": cold_step, "stages_ms": dict(zip(("fill", "conv3", "conv5"), cold)),
                        "Gparticles_s": n_p / (cold_step * 1e-3) / 1e9,
                        "pipeline_3x3x3": rate(cold[0] + cold[1]), "pipeline_5x5x5": rate(cold[0] + cold[2])},
