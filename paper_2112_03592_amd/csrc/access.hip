@@ -4,6 +4,7 @@
 // list of the convolution (the pre-pass of Section 5.2).
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "common.hpp"
 
@@ -351,6 +352,72 @@ static void free_handle(apr_handle* h) {
   delete h;
 }
 
+// Launch order of the convolution tiles.  A tile's cost is set by the number
+// of 64-cell chunks its sweep takes (each chunk is a fixed sequence of memory
+// rounds and barriers), counted here from the host copy of the access.  The
+// list (finest level first, then z, x) is cut into eight contiguous ranges of
+// equal chunk count, one per XCD (neighbouring tiles share halo rows in that
+// XCD's L2), and each range runs its heaviest tiles first, so that no long
+// tile starts last.
+static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream_t s) {
+  const int64_t n = h->n_tiles;
+  for (int x = 0; x <= 8; ++x) h->xcd_off[x] = n * x / 8;
+  if (n < 16) return APR_OK;
+  std::vector<uint64_t> t(size_t(n), 0);
+  APR_HIP(hipMemcpyAsync(t.data(), h->tiles, size_t(n) * 8, hipMemcpyDeviceToHost, s));
+  APR_HIP(hipStreamSynchronize(s));
+  const Meta& m = h->meta;
+  std::vector<uint32_t> chunks(size_t(n), 0);
+  std::vector<uint64_t> bits;
+  for (int64_t i = 0; i < n; ++i) {
+    int l, tz, tx, y0;
+    tile_unpack(t[size_t(i)], l, tz, tx, y0);
+    const int words = (m.dy[l] + 63) / 64;
+    bits.assign(size_t(words), 0);
+    for (int z = tz * kTileZ; z < std::min(m.dz[l], (tz + 1) * kTileZ); ++z)
+      for (int x = tx * kTileX; x < std::min(m.dx[l], (tx + 1) * kTileX); ++x) {
+        const uint64_t row = uint64_t(m.prow[l]) + uint64_t(z) * uint64_t(m.dx[l]) + uint64_t(x);
+        const uint64_t b = row ? d->xz_end[row - 1] : 0, e = d->xz_end[row];
+        for (uint64_t j = b; j < e; ++j) bits[d->y_idx[j] >> 6] |= uint64_t(1) << (d->y_idx[j] & 63);
+      }
+    // first occupied y at or after y (or -1)
+    auto next = [&](int y) {
+      for (int w = y >> 6; w < words; ++w) {
+        uint64_t v = bits[size_t(w)];
+        if (w == (y >> 6)) v &= ~uint64_t(0) << (y & 63);
+        if (v) return w * 64 + __builtin_ctzll(v);
+      }
+      return -1;
+    };
+    uint32_t c = 0;
+    for (int y = next(0); y >= 0; y = (y + 64 < m.dy[l]) ? next(y + 64) : -1) ++c;
+    chunks[size_t(i)] = std::max<uint32_t>(c, 1);
+  }
+  uint64_t total = 0;
+  for (uint32_t c : chunks) total += c;
+  int64_t off[9];
+  off[0] = 0;
+  off[8] = n;
+  uint64_t acc = 0;
+  int x = 1;
+  for (int64_t i = 0; i < n && x < 8; ++i) {
+    acc += chunks[size_t(i)];
+    while (x < 8 && acc * 8 >= total * uint64_t(x)) off[x++] = i + 1;
+  }
+  while (x < 8) off[x++] = n;
+  std::vector<int64_t> idx(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) idx[size_t(i)] = i;
+  for (int r = 0; r < 8; ++r)
+    std::stable_sort(idx.begin() + off[r], idx.begin() + off[r + 1],
+                     [&](int64_t a, int64_t b) { return chunks[size_t(a)] > chunks[size_t(b)]; });
+  std::vector<uint64_t> sorted(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) sorted[size_t(i)] = t[size_t(idx[size_t(i)])];
+  APR_HIP(hipMemcpyAsync(h->tiles, sorted.data(), size_t(n) * 8, hipMemcpyHostToDevice, s));
+  APR_HIP(hipStreamSynchronize(s));
+  for (int r = 0; r <= 8; ++r) h->xcd_off[r] = off[r];
+  return APR_OK;
+}
+
 #define APR_TRY(expr)                 \
   do {                                \
     apr_status _s = (expr);           \
@@ -593,6 +660,7 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
     hipLaunchKernelGGL(tile_compact_kernel, dim3(unsigned((ntot + 255) / 256)), dim3(256), 0, s,
                        tl, sc, raw, ymin, h->tiles, ntot);
     APR_TRY_HIP(hipGetLastError());
+    APR_TRY(order_tiles(h, d, s));
   }
   // ---- gather maps (multichannel convolution and the backward passes)
   for (int gi = 0; gi < 2; ++gi) {

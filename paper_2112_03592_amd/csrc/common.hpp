@@ -156,8 +156,9 @@ struct apr_handle {
   uint32_t* pend = nullptr;   // particle row ends [n_rows]
   uint16_t* ty = nullptr;     // tree y [n_t]
   uint32_t* tend = nullptr;   // tree row ends [n_trows]
-  uint64_t* tiles = nullptr;  // conv tiles [n_tiles], finest level first
+  uint64_t* tiles = nullptr;  // conv tiles [n_tiles]: eight XCD ranges, heaviest first in each
   int64_t n_tiles = 0;
+  int64_t xcd_off[9] = {0};   // tiles of XCD x: [xcd_off[x], xcd_off[x + 1])
   int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]
   uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t]
   // inverse of the gather maps for the coarse and tree taps: for source s

@@ -21,6 +21,7 @@
 // no atomics.  Threads share data through LDS only (outputs are never read
 // back), so the barriers order LDS and leave stores in flight.  The blockIdx -> tile map gives each XCD a contiguous run of
 // tiles so that halo rows shared by neighbouring tiles hit the same L2.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.hpp"
@@ -50,6 +51,7 @@ struct ConvArgs {
   const uint32_t* tend;
   const uint64_t* tiles;
   int64_t n_tiles;
+  int64_t xcd_off[9];     // tiles of XCD x: [xcd_off[x], xcd_off[x + 1])
   const void* x;
   const void* tree;
   const float* w;
@@ -146,11 +148,11 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
   const int wave = tid >> 6;
   const uint32_t lane = lane_id();
 
-  // XCD-aware tile order: block b runs on XCD b % 8; give each XCD a
-  // contiguous range of tiles.
-  const int64_t per = (a.n_tiles + 7) / 8;
-  const int64_t t = int64_t(blockIdx.x % 8) * per + int64_t(blockIdx.x / 8);
-  if (t >= a.n_tiles) return;
+  // XCD-aware tile order: block b runs on XCD b % 8, which takes its own
+  // contiguous range of the tile list (equal work per XCD, heaviest first).
+  const int xcd = int(blockIdx.x % 8);
+  const int64_t t = a.xcd_off[xcd] + int64_t(blockIdx.x / 8);
+  if (t >= a.xcd_off[xcd + 1]) return;
   int l, tz, tx, ty0;
   tile_unpack(a.tiles[t], l, tz, tx, ty0);
   // workgroup-uniform: keep them in scalar registers
@@ -477,7 +479,8 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
 
 template <int K, bool INDEX>
 static apr_status launch_conv(const ConvArgs& args, int xdt, int ydt, hipStream_t s) {
-  const int64_t per = (args.n_tiles + 7) / 8;
+  int64_t per = 0;
+  for (int x = 0; x < 8; ++x) per = std::max(per, args.xcd_off[x + 1] - args.xcd_off[x]);
   const dim3 grid(unsigned(per * 8));
   if (!INDEX && args.epi == APR_EPI_GRADMAG) {
     if (K != 3) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: APR_EPI_GRADMAG needs k = 3");
@@ -513,6 +516,7 @@ static ConvArgs base_args(const apr_handle* h) {
   a.tend = h->tend;
   a.tiles = h->tiles;
   a.n_tiles = h->n_tiles;
+  for (int x = 0; x <= 8; ++x) a.xcd_off[x] = h->xcd_off[x];
   a.n_wlevels = 1;
   return a;
 }
