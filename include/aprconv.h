@@ -97,9 +97,12 @@ typedef struct apr_handle apr_handle;
  * tree (all interior nodes, Section 3.4: for every tree row the sorted union of
  * y/2 over the particles and tree nodes of its 2x2 child rows, finest level
  * first), the list of non-empty convolution tiles (the non-empty-row
- * pre-pass of Section 5.2, with each tile's first particle y) and the child
- * list of every tree node (which apr_fill_tree gathers over).  Optional device validation per `desc->flags`
- * returns APR_EPARTITION / APR_EUNBALANCED.  Synchronizes `stream` once before
+ * pre-pass of Section 5.2, with each tile's first particle y; ordered for
+ * launch as eight contiguous ranges of equal work, one per XCD, heaviest tiles
+ * first, the work of a tile being the number of 64-cell chunks of its y sweep,
+ * counted on the host) and the child list of every tree node (which
+ * apr_fill_tree gathers over).  Optional device validation per `desc->flags`
+ * returns APR_EPARTITION / APR_EUNBALANCED.  Synchronizes `stream` before
  * returning.  The handle owns all its device memory; it is immutable after
  * the build and may be used from several streams.  Free with
  * apr_access_destroy. */
