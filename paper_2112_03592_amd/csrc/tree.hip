@@ -170,7 +170,7 @@ __device__ inline void fill_node(const uint32_t* __restrict__ cmap, int64_t n_t,
 
 constexpr int kFillFlat = 256;
 constexpr int kFillSmallThreads = 1024;
-constexpr int64_t kFillSmall = 16384;   // coarse levels up to this many nodes in all go to one workgroup
+constexpr int64_t kFillSmall = 1024;    // coarse levels up to this many nodes in all go to one workgroup
 
 // one tree level, one lane per node
 template <typename T, int CH>
