@@ -116,6 +116,23 @@ apr_status apr_access_get_info(const apr_handle* h, apr_access_info* out);
  * tree levels).  Either pointer may be NULL.  Synchronous. */
 apr_status apr_access_export_tree(const apr_handle* h, uint16_t* tree_y_idx, uint64_t* tree_xz_end);
 
+/* Copy one of the handle's canonical arrays to host memory (synchronous):
+ *  APR_EXPORT_APR:   a = uint16 y_idx [n_particles], b = uint64 xz_end [n_rows]
+ *                    (the LinearAccess of Algorithm 1 the handle was built from);
+ *  APR_EXPORT_TREE:  a = uint16 tree_y_idx [n_tree], b = uint64 tree_xz_end
+ *                    [n_tree_rows] (as apr_access_export_tree);
+ *  APR_EXPORT_TILES: a = int32 [n_tiles][4] (level, tile z, tile x, first
+ *                    particle y) of every tile of 8 x 8 (z, x) rows of one
+ *                    level that holds a particle (Section 5.2's non-empty-row
+ *                    pre-pass; tile (tz, tx) covers rows z in [8 tz, 8 tz + 8),
+ *                    x in [8 tx, 8 tx + 8)), in launch order; b = int64 [9],
+ *                    the start of each XCD's range of that list, then its end.
+ * Either pointer may be NULL.  Unknown `which`: APR_EINVAL. */
+#define APR_EXPORT_APR 0
+#define APR_EXPORT_TREE 1
+#define APR_EXPORT_TILES 2
+apr_status apr_access_export(const apr_handle* h, int32_t which, void* a, void* b);
+
 /* Release the handle and its device memory. NULL is accepted. */
 apr_status apr_access_destroy(apr_handle* h);
 

@@ -260,13 +260,15 @@ def apr_conv_bwd_data(apr: LinearAccess, dy, w, tree: Optional[LinearAccess] = N
 
 
 def apr_conv_bwd_weight(apr: LinearAccess, x, dy, k: int, n_wlevels: Optional[int] = None,
-                        tree: Optional[LinearAccess] = None) -> np.ndarray:
+                        tree: Optional[LinearAccess] = None, tvals=None) -> np.ndarray:
     """dW_l[co, ci, o] = sum_{p at level l} dY[p, co] V_l[ci](c_p + o).
-    With one shared stencil (n_wlevels == 1) the levels are summed."""
+    With one shared stencil (n_wlevels == 1) the levels are summed.  ``tvals``
+    (tree values of x, e.g. as stored in a narrower type) replaces the FP64
+    fill when given."""
     tree = tree_structure(apr) if tree is None else tree
     x2 = _as2d(x)
     g = _as2d(dy)
-    t2 = _as2d(fill_tree(apr, tree, x2))
+    t2 = _as2d(fill_tree(apr, tree, x2)) if tvals is None else _as2d(tvals)
     r = (k - 1) // 2
     nl = apr.l_max - apr.l_min + 1
     dW = np.zeros((nl, g.shape[1], x2.shape[1], k, k, k))

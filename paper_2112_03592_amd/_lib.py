@@ -20,9 +20,13 @@ APR_MAX_LEVELS = 17
 APR_STENCIL_SAME, APR_STENCIL_RESTRICT, APR_STENCIL_ADAPTIVE = 0, 1, 2
 APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL, APR_EPI_MULPOW, APR_EPI_GRADMAG = 0, 1, 2, 3, 4
 
-EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree", "apr_access_destroy",
+APR_EXPORT_APR, APR_EXPORT_TREE, APR_EXPORT_TILES = 0, 1, 2
+
+EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree", "apr_access_export",
+            "apr_access_destroy",
             "apr_fill_tree", "apr_stencil_levels", "apr_conv", "apr_neighbor_map",
-            "apr_richardson_lucy_workspace", "apr_richardson_lucy", "apr_conv_bwd_data",
+            "apr_richardson_lucy_workspace", "apr_richardson_lucy",
+            "apr_conv_bwd_data",
             "apr_conv_bwd_weight_ws", "apr_conv_bwd_weight", "apr_nn_workspace", "apr_moments",
             "apr_pointwise", "apr_relu_bias_grad", "apr_rel_l2", "apr_adam", "apr_level_weights",
             "apr_last_error"]
@@ -73,6 +77,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.apr_access_build.argtypes = [POINTER(AccessDesc), c_void_p, POINTER(c_void_p)]
     lib.apr_access_get_info.argtypes = [c_void_p, POINTER(AccessInfo)]
     lib.apr_access_export_tree.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.apr_access_export.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
     lib.apr_access_destroy.argtypes = [c_void_p]
     lib.apr_fill_tree.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]
     lib.apr_stencil_levels.argtypes = [c_int32, c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32,

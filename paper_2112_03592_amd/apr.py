@@ -95,6 +95,23 @@ class AprAccess:
                                                  te.ctypes.data if te.size else None))
         return ty, te
 
+    def export_apr(self):
+        """The particle LinearAccess held by the handle (``apr_access_export``)."""
+        y = np.zeros(self.n_particles, np.uint16)
+        e = np.zeros(self.n_rows, np.uint64)
+        L.check(self._lib.apr_access_export(self.handle, L.APR_EXPORT_APR, y.ctypes.data if y.size else None,
+                                            e.ctypes.data if e.size else None))
+        return y, e
+
+    def export_tiles(self):
+        """Tile list [n_tiles, 4] (level, tile z, tile x, first y) in launch
+        order and the XCD range starts [9]."""
+        t = np.zeros((self.n_tiles, 4), np.int32)
+        off = np.zeros(9, np.int64)
+        L.check(self._lib.apr_access_export(self.handle, L.APR_EXPORT_TILES, t.ctypes.data if t.size else None,
+                                            off.ctypes.data))
+        return t, off
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             self._lib.apr_access_destroy(self._h)
@@ -263,6 +280,7 @@ def richardson_lucy(acc: AprAccess, u: torch.Tensor, psf, n_iter: int, eps_rel: 
     L.check(acc._lib.apr_richardson_lucy(acc.handle, k, w.shape[0], _ptr(w), _ptr(wf), _ptr(u), _ptr(init), _ptr(out),
                                          int(n_iter), float(eps_rel), float(power), _ptr(ws), _stream()))
     return out
+
 
 
 # ---------------------------------------------------------------------------

@@ -742,6 +742,43 @@ apr_status apr_access_export_tree(const apr_handle* h, uint16_t* ty, uint64_t* t
   return APR_OK;
 }
 
+apr_status apr_access_export(const apr_handle* h, int32_t which, void* a, void* b) {
+  if (!h) APR_FAIL(APR_EINVAL, "apr_access_export: null handle");
+  switch (which) {
+    case APR_EXPORT_APR: {
+      if (a && h->n_p) APR_HIP(hipMemcpy(a, h->py, size_t(h->n_p) * 2, hipMemcpyDeviceToHost));
+      if (b && h->n_rows) {
+        std::vector<uint32_t> e(static_cast<size_t>(h->n_rows));
+        APR_HIP(hipMemcpy(e.data(), h->pend, size_t(h->n_rows) * 4, hipMemcpyDeviceToHost));
+        uint64_t* out = static_cast<uint64_t*>(b);
+        for (int64_t i = 0; i < h->n_rows; ++i) out[i] = e[size_t(i)];
+      }
+      return APR_OK;
+    }
+    case APR_EXPORT_TREE:
+      return apr_access_export_tree(h, static_cast<uint16_t*>(a), static_cast<uint64_t*>(b));
+    case APR_EXPORT_TILES: {
+      if (a && h->n_tiles) {
+        std::vector<uint64_t> t(static_cast<size_t>(h->n_tiles));
+        APR_HIP(hipMemcpy(t.data(), h->tiles, size_t(h->n_tiles) * 8, hipMemcpyDeviceToHost));
+        int32_t* out = static_cast<int32_t*>(a);
+        for (int64_t i = 0; i < h->n_tiles; ++i) {
+          int l, tz, tx, y0;
+          apr::tile_unpack(t[size_t(i)], l, tz, tx, y0);
+          out[4 * i] = l;
+          out[4 * i + 1] = tz;
+          out[4 * i + 2] = tx;
+          out[4 * i + 3] = y0;
+        }
+      }
+      if (b) std::copy(h->xcd_off, h->xcd_off + 9, static_cast<int64_t*>(b));
+      return APR_OK;
+    }
+    default:
+      APR_FAIL(APR_EINVAL, "apr_access_export: which must be APR_EXPORT_APR, APR_EXPORT_TREE or APR_EXPORT_TILES");
+  }
+}
+
 apr_status apr_access_destroy(apr_handle* h) {
   free_handle(h);
   return APR_OK;

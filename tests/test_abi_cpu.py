@@ -112,3 +112,9 @@ def test_binding_constants_match_the_header():
     for n in names:
         if n in defined:
             assert getattr(L, n) == defined[n], n
+
+
+def test_export_rejects_bad_arguments():
+    lib = L.load()
+    assert lib.apr_access_export(None, L.APR_EXPORT_APR, None, None) == L.APR_EINVAL
+    assert b"null handle" in lib.apr_last_error()

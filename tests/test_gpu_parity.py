@@ -59,6 +59,29 @@ def test_tree_structure_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_export_apr_and_tiles(name):
+    """The particle LinearAccess round-trips bit-exactly; the tile list is
+    the set of 8 x 8-row tiles of each level that hold a particle, each with
+    the smallest y of its particles, split into eight launch ranges."""
+    say("export", name)
+    inp, la, tr = case(name)
+    with G.AprAccess.from_input(inp) as acc:
+        y, e = acc.export_apr()
+        tiles, off = acc.export_tiles()
+    assert np.array_equal(y, inp.y_idx) and np.array_equal(e, inp.xz_end)
+    want = {}
+    for l in range(la.l_min, la.l_max + 1):
+        c = la.cells(l)
+        for (z, x, yy) in c:
+            key = (l, int(z) // 8, int(x) // 8)
+            want[key] = min(want.get(key, 1 << 30), int(yy))
+    got = {(int(t[0]), int(t[1]), int(t[2])): int(t[3]) for t in tiles}
+    assert len(got) == tiles.shape[0], "a tile is listed twice"
+    assert got == want
+    assert off[0] == 0 and off[8] == tiles.shape[0] and np.all(np.diff(off) >= 0)
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
 def test_fill_tree_fp32(name):
     say("fill tree", name)
     inp, la, tr = case(name)
