@@ -270,6 +270,21 @@ apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_t n_wlevels
                                const float* w_flip, const float* u, const float* init, float* out,
                                int32_t n_iter, float eps_rel, float power, void* work, void* stream);
 
+/* Allocation-free variant of apr_richardson_lucy, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and results as
+ * apr_richardson_lucy without `work`: the workspace is a static device array
+ * of APR_RL_STATIC_FLOATS floats (64 MiB) per GPU, held until the process
+ * ends, so the handle must satisfy N_t + 3 N_p + 1088 <= APR_RL_STATIC_FLOATS
+ * (about 5.3M particles); larger handles return APR_EINVAL and launch
+ * nothing.  Calls no allocating routine.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (several streams or threads)
+ * race and give undefined results; serialize them.  Asynchronous. */
+#define APR_RL_STATIC_FLOATS (1u << 24)
+apr_status apr_richardson_lucy_static(const apr_handle* h, int32_t k, int32_t n_wlevels, const float* w,
+                                      const float* w_flip, const float* u, const float* init, float* out,
+                                      int32_t n_iter, float eps_rel, float power, void* stream);
+
 /* ----------------------------------------------------------------------
  * Learned surrogate support.  Section 7 proposes CNNs made of APR
  * convolution layers whose filters are learned per resolution level by

@@ -19,13 +19,14 @@ APR_VALIDATE_PARTITION, APR_VALIDATE_BALANCE, APR_BUILD_GATHER3, APR_BUILD_GATHE
 APR_MAX_LEVELS = 17
 APR_STENCIL_SAME, APR_STENCIL_RESTRICT, APR_STENCIL_ADAPTIVE = 0, 1, 2
 APR_EPI_NONE, APR_EPI_RATIO, APR_EPI_MUL, APR_EPI_MULPOW, APR_EPI_GRADMAG = 0, 1, 2, 3, 4
+APR_RL_STATIC_FLOATS = 1 << 24
 
 APR_EXPORT_APR, APR_EXPORT_TREE, APR_EXPORT_TILES = 0, 1, 2
 
 EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree", "apr_access_export",
             "apr_access_destroy",
             "apr_fill_tree", "apr_stencil_levels", "apr_conv", "apr_neighbor_map",
-            "apr_richardson_lucy_workspace", "apr_richardson_lucy",
+            "apr_richardson_lucy_workspace", "apr_richardson_lucy", "apr_richardson_lucy_static",
             "apr_conv_bwd_data",
             "apr_conv_bwd_weight_ws", "apr_conv_bwd_weight", "apr_nn_workspace", "apr_moments",
             "apr_pointwise", "apr_relu_bias_grad", "apr_rel_l2", "apr_adam", "apr_level_weights",
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.apr_richardson_lucy_workspace.restype = ctypes.c_size_t
     lib.apr_richardson_lucy.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_void_p, c_int32, c_float, c_float, c_void_p, c_void_p]
+    lib.apr_richardson_lucy_static.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                               c_void_p, c_int32, c_float, c_float, c_void_p]
     lib.apr_conv_bwd_data.argtypes = [c_void_p, POINTER(ConvDesc), c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p]
     lib.apr_conv_bwd_weight_ws.argtypes = [c_void_p, POINTER(ConvDesc)]

@@ -282,6 +282,19 @@ def richardson_lucy(acc: AprAccess, u: torch.Tensor, psf, n_iter: int, eps_rel: 
     return out
 
 
+def richardson_lucy_static(acc: AprAccess, u: torch.Tensor, w: torch.Tensor, w_flip: torch.Tensor, n_iter: int,
+                           out: torch.Tensor, eps_rel: float = 1e-12, init: Optional[torch.Tensor] = None,
+                           power: float = 1.0) -> torch.Tensor:
+    """``apr_richardson_lucy_static``: the same iterations on the library's
+    static per-device scratch (no device allocation in the call).  w, w_flip:
+    FP32 per-level PSF and flipped PSF [nw, k, k, k] already on the device
+    (``stencil_levels`` with "restrict"); out: a caller-allocated FP32 [N_p]."""
+    k = int(w.shape[-1])
+    L.check(acc._lib.apr_richardson_lucy_static(acc.handle, k, int(w.shape[0]), _ptr(w), _ptr(w_flip), _ptr(u),
+                                                _ptr(init), _ptr(out), int(n_iter), float(eps_rel), float(power),
+                                                _stream()))
+    return out
+
 
 # ---------------------------------------------------------------------------
 # Surrogate network support (apr_moments ... apr_level_weights)

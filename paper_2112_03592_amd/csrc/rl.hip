@@ -2,6 +2,8 @@
 // the tree-fill and convolution kernels, with the quotient and the update
 // fused into the convolution epilogues.
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "common.hpp"
 
@@ -45,21 +47,15 @@ extern "C" size_t apr_richardson_lucy_workspace(const apr_handle* h) {
   return (nt + 3 * np + 1024 + 64) * sizeof(float) + 256;
 }
 
-extern "C" apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_t n_wlevels,
-                                          const float* w, const float* w_flip, const float* u,
-                                          const float* init, float* out, int32_t n_iter, float eps_rel,
-                                          float power, void* work, void* stream) {
-  if (!h || !w || !w_flip || !u || !out || !work) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: null argument");
-  if (n_iter < 0) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: n_iter < 0");
-  if (!(power > 0.f) || !(power < 16.f)) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: power must be in (0, 16)");
-  if (out == u || (init && out == init))
-    APR_FAIL(APR_EINVAL, "apr_richardson_lucy: out must not alias u or init");
+namespace apr {
+// The iterations over a workspace whose start `base` is 256-byte aligned and
+// holds (N_t + 3 N_p + 1088) floats: tree [N_t] | rho [N_p] | ping [N_p] |
+// pong [N_p] | block maxima [1024] | eps.
+static apr_status rl_run(const apr_handle* h, int32_t k, int32_t n_wlevels, const float* w, const float* w_flip,
+                         const float* u, const float* init, float* out, int32_t n_iter, float eps_rel, float power,
+                         char* base, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t np = h->n_p;
-  if (np == 0) return APR_OK;
-  // workspace: tree [N_t] | rho [N_p] | ping [N_p] | pong [N_p] | block maxima | eps
-  char* base = static_cast<char*>(work);
-  base += (256 - (reinterpret_cast<uintptr_t>(base) & 255)) & 255;
   float* tree = reinterpret_cast<float*>(base);
   float* rho = tree + h->n_t;
   float* ping = rho + np;
@@ -103,4 +99,69 @@ extern "C" apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_
     APR_HIP(hipGetLastError());
   }
   return APR_OK;
+}
+
+static apr_status rl_check(const apr_handle* h, const float* w, const float* w_flip, const float* u,
+                           const float* init, float* out, int32_t n_iter, float power, const char* who) {
+  if (!h || !w || !w_flip || !u || !out) APR_FAIL(APR_EINVAL, std::string(who) + ": null argument");
+  if (n_iter < 0) APR_FAIL(APR_EINVAL, std::string(who) + ": n_iter < 0");
+  if (!(power > 0.f) || !(power < 16.f)) APR_FAIL(APR_EINVAL, std::string(who) + ": power must be in (0, 16)");
+  if (out == u || (init && out == init)) APR_FAIL(APR_EINVAL, std::string(who) + ": out must not alias u or init");
+  return APR_OK;
+}
+
+// Scratch of the allocation-free variant: one array per device, held until
+// the process ends.  Host code never names it directly: the device address
+// comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) float scratch[APR_RL_STATIC_FLOATS];
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[64] = {nullptr};
+
+static apr_status scratch_for_current_device(float** out) {
+  int dev = 0;
+  APR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) APR_FAIL(APR_EUNSUPPORTED, "apr_richardson_lucy_static: device index >= 64");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      APR_FAIL(APR_EDEVICE, std::string("apr_richardson_lucy_static: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return APR_OK;
+}
+}  // namespace apr
+
+extern "C" apr_status apr_richardson_lucy(const apr_handle* h, int32_t k, int32_t n_wlevels,
+                                          const float* w, const float* w_flip, const float* u,
+                                          const float* init, float* out, int32_t n_iter, float eps_rel,
+                                          float power, void* work, void* stream) {
+  apr_status st = rl_check(h, w, w_flip, u, init, out, n_iter, power, "apr_richardson_lucy");
+  if (st != APR_OK) return st;
+  if (!work) APR_FAIL(APR_EINVAL, "apr_richardson_lucy: null workspace");
+  if (h->n_p == 0) return APR_OK;
+  char* base = static_cast<char*>(work);
+  base += (256 - (reinterpret_cast<uintptr_t>(base) & 255)) & 255;
+  return rl_run(h, k, n_wlevels, w, w_flip, u, init, out, n_iter, eps_rel, power, base, stream);
+}
+
+extern "C" apr_status apr_richardson_lucy_static(const apr_handle* h, int32_t k, int32_t n_wlevels,
+                                                 const float* w, const float* w_flip, const float* u,
+                                                 const float* init, float* out, int32_t n_iter, float eps_rel,
+                                                 float power, void* stream) {
+  apr_status st = rl_check(h, w, w_flip, u, init, out, n_iter, power, "apr_richardson_lucy_static");
+  if (st != APR_OK) return st;
+  const uint64_t need = uint64_t(h->n_t) + 3 * uint64_t(h->n_p) + 1024 + 64;
+  if (need > uint64_t(APR_RL_STATIC_FLOATS))
+    APR_FAIL(APR_EINVAL, "apr_richardson_lucy_static: N_t + 3 N_p + 1088 = " + std::to_string(need) +
+                             " floats exceeds the static scratch of " + std::to_string(APR_RL_STATIC_FLOATS) +
+                             " floats; use apr_richardson_lucy with a workspace");
+  if (h->n_p == 0) return APR_OK;
+  float* base = nullptr;
+  st = scratch_for_current_device(&base);
+  if (st != APR_OK) return st;
+  return rl_run(h, k, n_wlevels, w, w_flip, u, init, out, n_iter, eps_rel, power, reinterpret_cast<char*>(base),
+                stream);
 }
