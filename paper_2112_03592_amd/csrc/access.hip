@@ -352,22 +352,26 @@ static void free_handle(apr_handle* h) {
   delete h;
 }
 
-// Launch order of the convolution tiles.  A tile's cost is set by the number
-// of 64-cell chunks its sweep takes (each chunk is a fixed sequence of memory
-// rounds and barriers), counted here from the host copy of the access.  The
-// list (finest level first, then z, x) is cut into eight contiguous ranges of
-// equal chunk count, one per XCD (neighbouring tiles share halo rows in that
-// XCD's L2), and each range runs its heaviest tiles first, so that no long
-// tile starts last.
+// Sweep windows and launch order of the convolution tiles (host copy of the
+// access).  A tile's windows are the runs of its output y (union over the
+// tile's rows): a window spans at most kWinY cells and ends before a stretch
+// of more than kWinGap cells without outputs, so the patch is rebuilt only
+// around the outputs.  A tile's cost is taken as the cells its windows span
+// plus a fixed share per window (the memory rounds and barriers).  The list
+// (finest level first, then z, x) is cut into eight contiguous ranges of equal
+// cost, one per XCD (neighbouring tiles share halo rows in that XCD's L2), and
+// each range runs its heaviest tiles first, so that no long tile starts last.
 static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream_t s) {
   const int64_t n = h->n_tiles;
   for (int x = 0; x <= 8; ++x) h->xcd_off[x] = n * x / 8;
-  if (n < 16) return APR_OK;
+  if (n == 0) return APR_OK;
   std::vector<uint64_t> t(size_t(n), 0);
   APR_HIP(hipMemcpyAsync(t.data(), h->tiles, size_t(n) * 8, hipMemcpyDeviceToHost, s));
   APR_HIP(hipStreamSynchronize(s));
   const Meta& m = h->meta;
-  std::vector<uint32_t> chunks(size_t(n), 0);
+  std::vector<uint64_t> cost(size_t(n), 0);
+  std::vector<uint32_t> wins;           // windows, tile by tile in list order
+  std::vector<int64_t> woff(size_t(n) + 1, 0);
   std::vector<uint64_t> bits;
   for (int64_t i = 0; i < n; ++i) {
     int l, tz, tx, y0;
@@ -382,6 +386,7 @@ static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream
       }
     // first occupied y at or after y (or -1)
     auto next = [&](int y) {
+      if (y >= m.dy[l]) return -1;
       for (int w = y >> 6; w < words; ++w) {
         uint64_t v = bits[size_t(w)];
         if (w == (y >> 6)) v &= ~uint64_t(0) << (y & 63);
@@ -389,30 +394,55 @@ static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream
       }
       return -1;
     };
-    uint32_t c = 0;
-    for (int y = next(0); y >= 0; y = (y + 64 < m.dy[l]) ? next(y + 64) : -1) ++c;
-    chunks[size_t(i)] = std::max<uint32_t>(c, 1);
+    uint64_t c = 0;
+    for (int y = next(0); y >= 0;) {
+      const int w0 = y;
+      int last = y, nx;
+      while ((nx = next(last + 1)) >= 0 && nx - w0 < kWinY && nx - last - 1 <= kWinGap) last = nx;
+      wins.push_back(uint32_t(w0) | (uint32_t(last) << 16));
+      c += uint64_t(last - w0 + 1) + 16;
+      y = nx;
+    }
+    cost[size_t(i)] = std::max<uint64_t>(c, 1);
+    woff[size_t(i) + 1] = int64_t(wins.size());
   }
-  uint64_t total = 0;
-  for (uint32_t c : chunks) total += c;
   int64_t off[9];
-  off[0] = 0;
-  off[8] = n;
-  uint64_t acc = 0;
-  int x = 1;
-  for (int64_t i = 0; i < n && x < 8; ++i) {
-    acc += chunks[size_t(i)];
-    while (x < 8 && acc * 8 >= total * uint64_t(x)) off[x++] = i + 1;
-  }
-  while (x < 8) off[x++] = n;
+  for (int x = 0; x <= 8; ++x) off[x] = n * x / 8;
   std::vector<int64_t> idx(static_cast<size_t>(n));
   for (int64_t i = 0; i < n; ++i) idx[size_t(i)] = i;
-  for (int r = 0; r < 8; ++r)
-    std::stable_sort(idx.begin() + off[r], idx.begin() + off[r + 1],
-                     [&](int64_t a, int64_t b) { return chunks[size_t(a)] > chunks[size_t(b)]; });
+  if (n >= 16) {
+    uint64_t total = 0;
+    for (uint64_t c : cost) total += c;
+    off[0] = 0;
+    off[8] = n;
+    uint64_t acc = 0;
+    int x = 1;
+    for (int64_t i = 0; i < n && x < 8; ++i) {
+      acc += cost[size_t(i)];
+      while (x < 8 && acc * 8 >= total * uint64_t(x)) off[x++] = i + 1;
+    }
+    while (x < 8) off[x++] = n;
+    for (int r = 0; r < 8; ++r)
+      std::stable_sort(idx.begin() + off[r], idx.begin() + off[r + 1],
+                       [&](int64_t a, int64_t b) { return cost[size_t(a)] > cost[size_t(b)]; });
+  }
   std::vector<uint64_t> sorted(static_cast<size_t>(n));
-  for (int64_t i = 0; i < n; ++i) sorted[size_t(i)] = t[size_t(idx[size_t(i)])];
+  std::vector<uint32_t> swins(wins.size());
+  std::vector<uint32_t> soff(size_t(n) + 1, 0);
+  size_t k = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const size_t j = size_t(idx[size_t(i)]);
+    sorted[size_t(i)] = t[j];
+    for (int64_t q = woff[j]; q < woff[j + 1]; ++q) swins[k++] = wins[size_t(q)];
+    soff[size_t(i) + 1] = uint32_t(k);
+  }
+  h->n_wins = int64_t(wins.size());
+  apr_status st = dev_alloc(h, &h->wins, h->n_wins);
+  if (st == APR_OK) st = dev_alloc(h, &h->win_off, n + 1);
+  if (st != APR_OK) return st;
   APR_HIP(hipMemcpyAsync(h->tiles, sorted.data(), size_t(n) * 8, hipMemcpyHostToDevice, s));
+  APR_HIP(hipMemcpyAsync(h->wins, swins.data(), swins.size() * 4, hipMemcpyHostToDevice, s));
+  APR_HIP(hipMemcpyAsync(h->win_off, soff.data(), soff.size() * 4, hipMemcpyHostToDevice, s));
   APR_HIP(hipStreamSynchronize(s));
   for (int r = 0; r <= 8; ++r) h->xcd_off[r] = off[r];
   return APR_OK;

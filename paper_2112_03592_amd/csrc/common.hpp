@@ -39,6 +39,11 @@ __host__ __device__ inline void tile_unpack(uint64_t t, int& l, int& tz, int& tx
 
 constexpr int kTileZ = 8;   // output rows per tile along z
 constexpr int kTileX = 8;   // output rows per tile along x
+// The convolution sweeps a tile along y in windows: runs of output y (over the
+// tile's rows) spanning at most kWinY cells, a new window starting after a
+// stretch of more than kWinGap cells without outputs.
+constexpr int kWinY = 64;
+constexpr int kWinGap = 64;
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -158,6 +163,9 @@ struct apr_handle {
   uint32_t* tend = nullptr;   // tree row ends [n_trows]
   uint64_t* tiles = nullptr;  // conv tiles [n_tiles]: eight XCD ranges, heaviest first in each
   int64_t n_tiles = 0;
+  uint32_t* wins = nullptr;     // sweep windows of the tiles, in tile order: y0 | (y1 << 16)
+  uint32_t* win_off = nullptr;  // windows of tile t: [win_off[t], win_off[t + 1])
+  int64_t n_wins = 0;
   int64_t xcd_off[9] = {0};   // tiles of XCD x: [xcd_off[x], xcd_off[x + 1])
   int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]
   uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t]

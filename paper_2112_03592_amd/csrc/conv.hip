@@ -3,24 +3,25 @@
 //
 // Work item: one tile of kTileZ x kTileX particle rows (z, x) at one level l,
 // from the non-empty tile list (the pre-pass of Section 5.2).  A workgroup
-// (512 threads for 3^3, 1024 for 5^3) sweeps its tile along y in chunks; each chunk starts at the
-// smallest unprocessed y of the tile's output particles (empty stretches are
-// skipped) and spans at most kYC cells.  Per chunk:
-//   B. list the output particles of the centre rows that fall in
-//      [y0, y0 + kYC), and fetch the y at every source-row pointer;
-//   C. reconstruct the level-l patch of the halo rows in LDS over
-//      [y0 - r, ymax + r] from three sorted sources -- APR level l, tree level
-//      l (cells containing finer particles), APR level l-1 (each element covers
-//      2 x 2 x 2 level-l cells).  With 26-neighbour 2:1 balance these cover
-//      every cell within radius 2 of a level-l particle.  Elements of all
-//      source rows are spread flat over the threads (coalesced within a row),
-//      y and value fetched in one memory round;
-//   D. every listed particle accumulates its k^3 taps from the patch in FP32
-//      (weights in scalar registers) and writes its output.
-// Per-row bookkeeping uses one writer per row (the last element of a prefix),
-// no atomics.  Threads share data through LDS only (outputs are never read
-// back), so the barriers order LDS and leave stores in flight.  The blockIdx -> tile map gives each XCD a contiguous run of
-// tiles so that halo rows shared by neighbouring tiles hit the same L2.
+// sweeps its tile along y through the tile's windows, made at access build:
+// runs of the tile's output y spanning at most kWinY cells (empty stretches
+// are skipped, the per-block y-range of Section 5.2).
+//
+// The level-l patch of a window covers the halo rows of the tile over
+// [y0 - r, y1 + r] and is reconstructed in LDS from three sorted sources:
+// APR level l, tree level l (cells that contain finer particles) and APR
+// level l-1 (each element covers 2 x 2 x 2 level-l cells).  With 26-neighbour
+// 2:1 balance these cover every cell within radius 2 of a level-l particle.
+// Each source row is owned for the whole sweep by a group of lanes that keeps
+// the row's cursor in registers and moves a batch of consecutive elements per
+// memory round (coalesced, no searches); the first batch of the next window
+// is loaded while the current window's taps run.  A row whose cursor falls
+// far behind the window is advanced by a k-ary search, one probe per lane.
+// Centre-row particles of the window are appended to an output list (one LDS
+// atomic per wave), and every listed particle then accumulates its k^3 taps
+// from the patch in FP32 with the weights in scalar registers.  Two barriers
+// per window; barriers order LDS only (outputs are never read back, so stores
+// stay in flight).
 #include <algorithm>
 #include <type_traits>
 
@@ -28,19 +29,15 @@
 
 namespace apr {
 
-constexpr int kYC = 64;          // output cells per chunk along y
-constexpr int kBig = 1 << 28;    // y of an element past the end of its row
-// Launch shape per stencil size.  The kernel waits on memory most of the
-// time, so resident waves decide its speed: the 3^3 patch lets three
-// workgroups share a CU once registers are capped for six waves per SIMD;
-// the larger 5^3 patch allows two, so those workgroups are 1024 threads wide
-// (eight waves per SIMD).  Elements in flight per thread are set so that
-// nothing spills under those caps (spilled registers go through HBM).
+constexpr int kBig = 1 << 28;    // key of a missing element
+// Launch shape per stencil size.  Source rows are served by groups of kG
+// lanes; each group moves kG * kNB elements of its row per memory round.
 template <int K>
 struct ConvShape {
-  static constexpr int kThreads = K == 3 ? 512 : 1024;
-  static constexpr int kBatch = K == 3 ? 2 : 1;        // independent elements per thread in flight
-  static constexpr int kWavesPerSimd = K == 3 ? 6 : 8;
+  static constexpr int kThreads = 768;
+  static constexpr int kG = 8;
+  static constexpr int kNB = 2;
+  static constexpr int kWavesPerSimd = 6;
 };
 
 struct ConvArgs {
@@ -50,6 +47,8 @@ struct ConvArgs {
   const uint16_t* ty;
   const uint32_t* tend;
   const uint64_t* tiles;
+  const uint32_t* wins;      // sweep windows: y0 | (y1 << 16), outputs y0 <= y <= y1
+  const uint32_t* win_off;   // windows of tile t: [win_off[t], win_off[t + 1])
   int64_t n_tiles;
   int64_t xcd_off[9];     // tiles of XCD x: [xcd_off[x], xcd_off[x + 1])
   const void* x;
@@ -69,84 +68,49 @@ struct ConvArgs {
                         // n_sel holds N_p)
 };
 
-// exclusive scan of n LDS entries in place by one wave (E entries per lane,
-// n <= 64 * E); data[n] = total.  `fill(k)` yields the value of entry k.
-template <int E, typename F>
-__device__ inline void wave_scan_into(uint32_t* data, int n, F fill) {
-  const uint32_t lane = lane_id();
-  uint32_t v[E];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int k = int(lane) * E + q;
-    v[q] = (k < n) ? fill(k) : 0u;
-    sum += v[q];
-  }
-  uint32_t incl = sum;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(incl, o, 64);
-    if (lane >= uint32_t(o)) incl += t;
-  }
-  uint32_t run = incl - sum;
-#pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int k = int(lane) * E + q;
-    if (k < n) data[k] = run;
-    run += v[q];
-  }
-  if (lane == 63) data[n] = incl;
-}
-
-// largest r in [0, n) with pre[r] <= v (pre non-decreasing, pre[0] = 0 <= v)
-__device__ inline int find_row(const uint32_t* pre, int n, uint32_t v) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= v) lo = mid; else hi = mid;
-  }
-  return lo;
+// the G bits of lane group `gbase / G` in a wave ballot
+template <int G>
+__device__ inline uint32_t group_bits(uint64_t bal, uint32_t gbase) {
+  static_assert(G <= 16, "group masks are 32-bit");
+  return uint32_t(bal >> gbase) & ((1u << G) - 1u);
 }
 
 // NF = 3: three stencils per level on the same patch (the three directions of
 // a gradient filter), output the magnitude sqrt(sum of squares).
 template <int K, typename TX, typename TY, bool INDEX, int NF = 1>
 __global__ __launch_bounds__(ConvShape<K>::kThreads)
-__attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
-  constexpr int NT = ConvShape<K>::kThreads, NW = NT / 64;
-  constexpr int kBatch = ConvShape<K>::kBatch;
+__attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
+  constexpr int NT = ConvShape<K>::kThreads;
+  constexpr int G = ConvShape<K>::kG, NB = ConvShape<K>::kNB, GB = G * NB;
+  constexpr int NG = NT / G;                         // lane groups
   constexpr int R = K / 2;
-  constexpr int TZ = kTileZ, TX_ = kTileX;
-  constexpr int HZ = TZ + 2 * R, HX = TX_ + 2 * R;
+  constexpr int TZ = kTileZ, TXr = kTileX;
+  constexpr int HZ = TZ + 2 * R, HX = TXr + 2 * R;
   constexpr int NH = HZ * HX;                        // halo rows at level l
-  constexpr int PZ = ((TZ - 1 + R) >> 1) + 2;        // parent rows (level l-1)
-  constexpr int PX = ((TX_ - 1 + R) >> 1) + 2;
+  constexpr int PX = ((TXr - 1 + R) >> 1) + 2;       // parent rows (level l-1) per axis
+  constexpr int PZ = ((TZ - 1 + R) >> 1) + 2;
   constexpr int NCR = PZ * PX;
   constexpr int NSRC = 2 * NH + NCR;                 // [0,NH) APR l, [NH,2NH) tree l, rest APR l-1
-  constexpr int NC = TZ * TX_;                       // centre (output) rows
-  constexpr int PY = kYC + 2 * R;
+  constexpr int RPG = (NSRC + NG - 1) / NG;          // source rows per group
+  constexpr int NC = TZ * TXr;                       // centre (output) rows
+  constexpr int PY = kWinY + 2 * R;
   constexpr int K3 = K * K * K;
-  constexpr int OCAP = kYC + 1;                      // centre-row elements examined per chunk
-  constexpr int NOUT = NC * OCAP;
-  constexpr int ES = (NSRC + 63) / 64;               // scan entries per lane
-  constexpr uint16_t kUnlisted = 0xffffu;
+  constexpr uint32_t kNone = 0xffffffffu;
+  constexpr int kUnknown = -1;                       // y at the cursor not yet read
   using PT = typename std::conditional<INDEX, long long, float>::type;
-  static_assert(NC <= 64 && kYC == 64, "centre rows and offsets pack into 16 bits");
-  static_assert(NSRC < 65536 && NT >= NSRC, "one thread per source row");
+  static_assert(NC <= 64 && kWinY == 64, "output positions pack into 12 bits");
+  static_assert(64 % G == 0 && GB <= 32, "lane groups tile a wave; batch masks are 32-bit");
 
   __shared__ PT patch[NH * PY];
-  __shared__ uint32_t sp[NSRC], se[NSRC], spre[NSRC + 1], scons[NSRC];
-  __shared__ int yfirst[NSRC];
-  __shared__ uint8_t cmask[NCR];            // coarse row -> valid target halo rows (bit q: dz = q/2, dx = q%2)
-  __shared__ int16_t cbase[NCR];            // coarse row -> halo row of target q = 0
-  __shared__ uint32_t op[NC], oe[NC], opd[NC], ocnt[NC], opre[2][NC + 1];
-  __shared__ int rymax[NC], rnext[NC];      // per centre row: last listed y, next y
-  __shared__ uint16_t o_pos[NOUT];          // (centre row << 6) | (y - y0), or kUnlisted
-  __shared__ int s_y0;
+  __shared__ uint32_t o_idx[NC * kWinY];   // listed outputs of the window: particle index
+  __shared__ uint16_t o_pos[NC * kWinY];   // (centre row << 6) | (y - y0)
+  __shared__ uint32_t s_cnt[2];            // outputs listed, per window parity
 
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
   const uint32_t lane = lane_id();
+  const uint32_t gbase = lane & ~uint32_t(G - 1);   // first lane of this lane's group
+  const int gj = int(lane) - int(gbase);            // lane within the group
+  const int grp = tid / G;
 
   // XCD-aware tile order: block b runs on XCD b % 8, which takes its own
   // contiguous range of the tile list (equal work per XCD, heaviest first).
@@ -155,12 +119,13 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
   if (t >= a.xcd_off[xcd + 1]) return;
   int l, tz, tx, ty0;
   tile_unpack(a.tiles[t], l, tz, tx, ty0);
-  // workgroup-uniform: keep them in scalar registers
   l = __builtin_amdgcn_readfirstlane(l);
   tz = __builtin_amdgcn_readfirstlane(tz);
   tx = __builtin_amdgcn_readfirstlane(tx);
+  const uint32_t w_beg = __builtin_amdgcn_readfirstlane(a.win_off[t]);
+  const uint32_t w_end = __builtin_amdgcn_readfirstlane(a.win_off[t + 1]);
   const Meta& m = a.m;
-  const int z0 = tz * TZ, x0 = tx * TX_;
+  const int z0 = tz * TZ, x0 = tx * TXr;
   const int Dz = m.dz[l], Dx = m.dx[l], Dy = m.dy[l];
   const bool has_c = l > m.l_min;
   const bool has_t = l <= m.t_hi;
@@ -168,15 +133,22 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
   const TX* __restrict__ tv = static_cast<const TX*>(a.tree);
   const uint16_t* __restrict__ py = a.py;
   const uint16_t* __restrict__ ty = a.ty;
-  // per-level weights: read-only for the whole launch and uniform across the
-  // workgroup, so the tap loop reads them through scalar loads
   using cfloat = const __attribute__((address_space(4))) float;
   cfloat* wl = (cfloat*)(uintptr_t)(INDEX ? a.w : a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * K3 * NF);
-
-  // ---- setup
   const PT pad = INDEX ? PT(-1) : PT(0);
-  for (int i = tid; i < NH * PY; i += NT) patch[i] = pad;
-  for (int s = tid; s < NSRC; s += NT) {
+
+  // ---- setup: each group owns source rows s = grp + r * NG for the whole
+  // sweep.  Per row, in registers: the cursor (first element a later window
+  // may need), the end, the y at the cursor when known, and the first batch
+  // of the next window, loaded one window ahead.
+  uint32_t cur[RPG], end[RPG];
+  int ny[RPG];
+  bool act[RPG];
+  int pfy[RPG][NB];
+  PT pfv[RPG][NB];
+#pragma unroll
+  for (int r = 0; r < RPG; ++r) {
+    const int s = grp + r * NG;
     uint32_t b = 0, e = 0;
     if (s < 2 * NH) {
       const int h = s < NH ? s : s - NH;
@@ -184,226 +156,239 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
       const bool in = z >= 0 && x >= 0 && z < Dz && x < Dx;
       if (in && s < NH) row_range(a.pend, m.prow[l] + uint32_t(z) * Dx + x, b, e);
       if (in && s >= NH && has_t) row_range(a.tend, m.trow[l] + uint32_t(z) * Dx + x, b, e);
-    } else {
-      // the coarse element of parent row j covers halo rows
-      // hz = 2 * (j / PX) + R - 2 + {0, 1}, hx likewise; a halo row is a
-      // target if it lies in the halo and in the level-l grid (a coarse cell
-      // on the far edge of an odd-sized grid covers cells outside the image,
-      // which stay zero padding)
+    } else if (s < NSRC && has_c) {
       const int j = s - 2 * NH;
       const int pz = z0 / 2 - 1 + j / PX, px = x0 / 2 - 1 + j % PX;
-      if (has_c && pz >= 0 && px >= 0 && pz < m.dz[l - 1] && px < m.dx[l - 1])
+      if (pz >= 0 && px >= 0 && pz < m.dz[l - 1] && px < m.dx[l - 1])
         row_range(a.pend, m.prow[l - 1] + uint32_t(pz) * m.dx[l - 1] + px, b, e);
-      const int hz0 = 2 * (j / PX) + R - 2, hx0 = 2 * (j % PX) + R - 2;
-      int msk = 0;
-      for (int q = 0; q < 4; ++q) {
-        const int hz = hz0 + (q >> 1), hx = hx0 + (q & 1);
-        if (hz >= 0 && hx >= 0 && hz < HZ && hx < HX && z0 - R + hz < Dz && x0 - R + hx < Dx)
-          msk |= 1 << q;
-      }
-      cmask[j] = uint8_t(msk);
-      cbase[j] = int16_t(hz0 * HX + hx0);
     }
-    sp[s] = b;
-    se[s] = e;
-    scons[s] = 0;
+    cur[r] = b;
+    end[r] = e;
+    ny[r] = kUnknown;
+    act[r] = b < e;
   }
-  for (int c = tid; c < NC; c += NT) {
-    uint32_t b = 0, e = 0;
-    const int z = z0 + c / TX_, x = x0 + c % TX_;
-    if (z < Dz && x < Dx) row_range(a.pend, m.prow[l] + uint32_t(z) * Dx + x, b, e);
-    op[c] = b;
-    oe[c] = e;
-    ocnt[c] = 0;
-    rymax[c] = -1;
-    rnext[c] = int(kNoY);
+  // the first window's batches
+#pragma unroll
+  for (int r = 0; r < RPG; ++r) {
+    const int s = grp + r * NG;
+    const bool istree = s >= NH && s < 2 * NH;
+    const uint16_t* __restrict__ ys = istree ? ty : py;
+    const TX* __restrict__ vs = istree ? tv : xv;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const uint32_t i = cur[r] + uint32_t(u * G + gj);
+      const bool ok = act[r] && i < end[r];
+      pfy[r][u] = ok ? int(ys[i]) : kBig;
+      if constexpr (INDEX)
+        pfv[r][u] = PT((int64_t(s >= 2 * NH ? 2 : (istree ? 3 : 1)) << 40) | int64_t(i));
+      else
+        pfv[r][u] = ok ? to_f32<TX>(vs[i]) : 0.f;
+    }
   }
-  lds_barrier();
-  if (wave == 0) {
-    if (lane == 0) s_y0 = ty0;   // first y of the tile's particles, from the tile list
-    wave_scan_into<1>(opre[0], NC, [&](int c) { return min(oe[c] - op[c], uint32_t(OCAP)); });
+  // halo rows outside the level-l grid are zero padding for the whole sweep
+  // (no source ever writes them); other cells are written before use
+  for (int i = tid; i < NH * PY; i += NT) {
+    const int h = i / PY;
+    const int z = z0 - R + h / HX, x = x0 - R + h % HX;
+    if (z < 0 || x < 0 || z >= Dz || x >= Dx) patch[i] = pad;
   }
+  if (tid < 2) s_cnt[tid] = 0;
   lds_barrier();
 
   int par = 0;
-  while (true) {
-    const int y0 = s_y0;
-    if (y0 == int(kNoY)) break;
-    const uint32_t* ocap = opre[par];
-    const uint32_t nb = ocap[NC];
+  uint32_t wcur = a.wins[w_beg];
+  for (uint32_t wi = w_beg; wi < w_end; ++wi) {
+    const int y0 = int(wcur & 0xffffu), y1 = int(wcur >> 16);
+    const int wlo = y0 - R, whi = y1 + R;
+    const bool has_next = wi + 1 < w_end;
+    const uint32_t wnext = has_next ? a.wins[wi + 1] : 0u;
+    const int nwlo = int(wnext & 0xffffu) - R, nwhi = int(wnext >> 16) + R;
 
-    // ---- B (one memory round): the listed elements of a centre row are a
-    // prefix of its items; the last of them (or the first item, when none is
-    // listed) records the row's count, last y and next y.  Also fetch the y
-    // at every source-row pointer.
-    int yf = kBig;
-    if (tid < NSRC && sp[tid] < se[tid]) yf = (tid >= NH && tid < 2 * NH) ? int(ty[sp[tid]]) : int(py[sp[tid]]);
-    for (uint32_t base = tid; base < nb; base += NT * kBatch) {
-      int cc[kBatch], yv[kBatch], yn[kBatch];
-      uint32_t ii[kBatch], jj[kBatch];
+    // ---- sources: every element of the group's rows that covers a cell of
+    // [wlo, whi] is written into the level-l patch; centre-row particles in
+    // [y0, y1] are listed as outputs
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const uint32_t it = base + u * NT;
-        const bool ok = it < nb;
-        cc[u] = ok ? find_row(ocap, NC, it) : 0;
-        jj[u] = ok ? it - ocap[cc[u]] : 0u;
-        ii[u] = op[cc[u]] + jj[u];
-        yv[u] = ok ? int(py[ii[u]]) : 0;
-        yn[u] = (ok && ii[u] + 1 < oe[cc[u]]) ? int(py[ii[u] + 1]) : int(kNoY);
-      }
+    for (int r = 0; r < RPG; ++r) {
+      const int s = grp + r * NG;
+      const uint32_t e = end[r];
+      const bool coarse = s >= 2 * NH;
+      const int sh = coarse ? 1 : 0;   // element y covers cells [y << sh, ((y + 1) << sh) - 1]
+      if (s < NSRC && act[r]) {         // uniform per group
+        const bool istree = s >= NH && !coarse;
+        const uint16_t* __restrict__ ys = istree ? ty : py;
+        const TX* __restrict__ vs = istree ? tv : xv;
+        const int h = s < NH ? s : s - NH;
+        const bool centre = s < NH && h / HX >= R && h / HX < R + TZ && h % HX >= R && h % HX < R + TXr;
+        const int c = (h / HX - R) * TXr + (h % HX - R);
+        // coarse row: its element covers 2 x 2 halo rows from hb (mask of the
+        // ones inside the halo and the level-l grid)
+        int hb = 0, msk = 0;
+        if (coarse) {
+          const int j = s - 2 * NH;
+          const int hz0 = 2 * (j / PX) + R - 2, hx0 = 2 * (j % PX) + R - 2;
+          hb = hz0 * HX + hx0;
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const uint32_t it = base + u * NT;
-        if (it >= nb) continue;
-        const int c = cc[u];
-        if (yv[u] < y0 + kYC) {
-          o_pos[it] = uint16_t((c << 6) | (yv[u] - y0));
-          if (yn[u] >= y0 + kYC) {
-            ocnt[c] = jj[u] + 1;
-            rymax[c] = yv[u];
-            rnext[c] = yn[u];
+          for (int q = 0; q < 4; ++q) {
+            const int hz = hz0 + (q >> 1), hx = hx0 + (q & 1);
+            if (hz >= 0 && hx >= 0 && hz < HZ && hx < HX && z0 - R + hz < Dz && x0 - R + hx < Dx) msk |= 1 << q;
           }
+        }
+        uint32_t b = cur[r];
+        uint32_t keep = kNone;
+        int keep_y = kUnknown;
+        int yv[NB];
+        PT val[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          yv[u] = pfy[r][u];
+          val[u] = pfv[r][u];
+        }
+        bool more = true, loaded = true;
+        while (more) {
+          if (!loaded) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+              const uint32_t i = b + uint32_t(u * G + gj);
+              const bool ok = i < e;
+              yv[u] = ok ? int(ys[i]) : kBig;
+              if constexpr (INDEX)
+                val[u] = PT((int64_t(coarse ? 2 : (istree ? 3 : 1)) << 40) | int64_t(i));
+              else
+                val[u] = ok ? to_f32<TX>(vs[i]) : 0.f;
+            }
+          }
+          loaded = false;
+          uint32_t below = 0;
+#pragma unroll
+          for (int u = 0; u < NB; ++u)
+            below |= group_bits<G>(ballot(((yv[u] + 1) << sh) - 1 < wlo), gbase) << (u * G);
+          if (below == (1u << GB) - 1u && b + GB < e) {
+            // the whole batch lies before the window: k-ary search of
+            // [b + GB, e) for the first element covering a cell >= wlo
+            uint32_t lo = b + GB, hi = e;
+            while (hi - lo > uint32_t(GB)) {
+              const uint32_t span = hi - lo;
+              uint32_t bl = 0;
+#pragma unroll
+              for (int u = 0; u < NB; ++u) {
+                const uint32_t k = uint32_t(u * G + gj);
+                const uint32_t i = lo + span * (k + 1) / (GB + 1);
+                bl |= group_bits<G>(ballot(((int(ys[i]) + 1) << sh) - 1 < wlo), gbase) << (u * G);
+              }
+              const uint32_t n = __builtin_popcount(bl);   // probes below form a prefix
+              const uint32_t nlo = n ? lo + span * n / (GB + 1) + 1 : lo;
+              if (n < uint32_t(GB)) hi = lo + span * (n + 1) / (GB + 1);
+              lo = nlo;
+            }
+            b = lo;
+            continue;
+          }
+          // write the covered cells of the window; list outputs
+          bool isout[NB];
+          uint32_t nout = 0;
+          uint64_t ob[NB];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const int y = yv[u];
+            const bool ok = y != kBig;
+            if (ok && (y << sh) <= whi && ((y + 1) << sh) - 1 >= wlo) {
+              if (!coarse) {
+                patch[h * PY + (y - wlo)] = val[u];
+              } else {
+                const int c0 = 2 * y;
+                const bool w0 = c0 >= wlo, w1 = c0 + 1 <= whi && c0 + 1 < Dy;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  if (!((msk >> q) & 1)) continue;
+                  PT* row = patch + (hb + (q >> 1) * HX + (q & 1)) * PY - wlo;
+                  if (w0) row[c0] = val[u];
+                  if (w1) row[c0 + 1] = val[u];
+                }
+              }
+            }
+            isout[u] = centre && y >= y0 && y <= y1;
+            ob[u] = ballot(isout[u]);
+            nout += __builtin_popcountll(ob[u]);
+            // the next window's cursor: first element covering a cell >= its wlo
+            if (has_next) {
+              const uint32_t kb = group_bits<G>(ballot(ok && ((y + 1) << sh) - 1 >= nwlo), gbase);
+              if (keep == kNone && kb) {
+                keep = b + uint32_t(u * G) + uint32_t(__builtin_ctz(kb));
+                keep_y = __shfl(y, int(gbase) + __builtin_ctz(kb), 64);
+              }
+            }
+          }
+          if (nout) {   // uniform across the wave's active lanes
+            uint64_t all = 0;
+#pragma unroll
+            for (int u = 0; u < NB; ++u) all |= ob[u];
+            const int leader = __builtin_ctzll(all);
+            uint32_t base = 0;
+            if (int(lane) == leader) base = atomicAdd(&s_cnt[par], nout);
+            base = uint32_t(__shfl(int(base), leader, 64));
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+              if (isout[u]) {
+                const uint32_t slot = base + mask_rank(ob[u]);
+                o_idx[slot] = b + uint32_t(u * G + gj);
+                o_pos[slot] = uint16_t((c << 6) | (yv[u] - y0));
+              }
+              base += __builtin_popcountll(ob[u]);
+            }
+          }
+          // another batch if the row continues into the window
+          const int ylast = __shfl(yv[NB - 1], int(gbase) + G - 1, 64);
+          more = b + GB < e && ((ylast + 1) << sh) <= whi;
+          b += GB;
+        }
+        if (keep != kNone) {
+          cur[r] = keep;
+          ny[r] = keep_y;
         } else {
-          o_pos[it] = kUnlisted;
-          if (jj[u] == 0) rnext[c] = yv[u];
+          cur[r] = min(b, e);
+          ny[r] = kUnknown;
+        }
+      }
+      // is the row needed by the next window; if so, its first batch
+      if (s < NSRC) {
+        act[r] = has_next && cur[r] < e && (ny[r] == kUnknown || (ny[r] << sh) <= nwhi);
+        const bool istree = s >= NH && !coarse;
+        const uint16_t* __restrict__ ys = istree ? ty : py;
+        const TX* __restrict__ vs = istree ? tv : xv;
+        if (act[r]) {
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const uint32_t i = cur[r] + uint32_t(u * G + gj);
+            const bool ok = i < e;
+            pfy[r][u] = ok ? int(ys[i]) : kBig;
+            if constexpr (INDEX)
+              pfv[r][u] = PT((int64_t(coarse ? 2 : (istree ? 3 : 1)) << 40) | int64_t(i));
+            else
+              pfv[r][u] = ok ? to_f32<TX>(vs[i]) : 0.f;
+          }
         }
       }
     }
-    if (tid < NSRC) yfirst[tid] = yf;
-    lds_barrier();
-    // every wave reduces the per-row results itself (no extra barrier)
-    int ymax_c = (lane < uint32_t(NC)) ? rymax[lane] : -1;
-    int ynx = (lane < uint32_t(NC)) ? rnext[lane] : int(kNoY);
-    for (int o = 32; o > 0; o >>= 1) {
-      ymax_c = max(ymax_c, __shfl_xor(ymax_c, o, 64));
-      ynx = min(ynx, __shfl_xor(ynx, o, 64));
-    }
-    const int wlo = y0 - R, whi = ymax_c + R;
-    const int drop = (ynx == int(kNoY)) ? whi + 1 : ynx - R;   // cells below `drop` are never needed again
-
-    // ---- C0 (no memory round): wave 1 advances the centre pointers and sizes
-    // the next chunk's centre items; wave 0 sizes every source row's share
-    // of this window (y grows by >= 1 per element; a coarse element covers
-    // two cells); the other waves pad y outside the image
-    if (wave == 1) {
-      if (lane < uint32_t(NC)) {
-        opd[lane] = op[lane];
-        op[lane] += ocnt[lane];
-        ocnt[lane] = 0;
-      }
-      wave_lds_sync();
-      wave_scan_into<1>(opre[par ^ 1], NC, [&](int c) { return min(oe[c] - op[c], uint32_t(OCAP)); });
-    } else if (wave == 0) {
-      wave_scan_into<ES>(spre, NSRC, [&](int sr) -> uint32_t {
-        if (sp[sr] >= se[sr]) return 0u;
-        const int last = (sr >= 2 * NH) ? (whi >> 1) : whi;
-        const int yfs = yfirst[sr];
-        return (last >= yfs) ? min(uint32_t(last - yfs + 1), se[sr] - sp[sr]) : 0u;
-      });
-    } else if (wlo < 0 || whi >= Dy) {   // y outside the image is zero padding
-      const int span = whi - wlo + 1;
-      for (int j = tid - 128; j < NH * span; j += NT - 128) {
-        const int h = j / span, p = j % span;
-        const int yy = wlo + p;
-        if (yy < 0 || yy >= Dy) patch[h * PY + p] = pad;
+    // y outside the image is zero padding
+    if (wlo < 0 || whi >= Dy) {
+      for (int i = tid; i < NH * PY; i += NT) {
+        const int yy = wlo + i % PY;
+        if (yy < 0 || yy >= Dy) patch[i] = pad;
       }
     }
     lds_barrier();
 
-    // ---- C (one memory round): reconstruct the level-l patch over [wlo, whi]
-    const uint32_t ns = spre[NSRC];
-    const uint32_t nsf = spre[2 * NH];   // items of APR-l and tree-l rows come first
-    // fine sources: one patch cell per element
-    for (uint32_t base = tid; base < nsf; base += NT * kBatch) {
-      int ss[kBatch], yv[kBatch], yn[kBatch];
-      uint32_t ii[kBatch], jj[kBatch];
-      PT val[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const uint32_t it = base + u * NT;
-        const bool ok = it < nsf;
-        ss[u] = ok ? find_row(spre, NSRC, it) : 0;
-        jj[u] = ok ? it - spre[ss[u]] : 0u;
-        ii[u] = sp[ss[u]] + jj[u];
-        const bool istree = ss[u] >= NH;
-        const uint16_t* ys = istree ? ty : py;
-        yv[u] = ok ? int(ys[ii[u]]) : kBig;
-        // next element of the row, if it is one of this chunk's items
-        const bool has_next = ok && jj[u] + 1 < spre[ss[u] + 1] - spre[ss[u]];
-        yn[u] = has_next ? int(ys[ii[u] + 1]) : kBig;
-        if constexpr (INDEX)
-          val[u] = PT((int64_t(istree ? 3 : 1) << 40) | int64_t(ii[u]));
-        else
-          val[u] = ok ? to_f32<TX>((istree ? tv : xv)[ii[u]]) : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        if (base + u * NT >= nsf) continue;
-        const int s = ss[u];
-        if (yv[u] >= wlo && yv[u] <= whi) patch[(s >= NH ? s - NH : s) * PY + (yv[u] - wlo)] = val[u];
-        // consumed elements are a prefix of the row's items: the last one
-        // records the count
-        if (yv[u] < drop && !(yn[u] < drop)) scons[s] = jj[u] + 1;
-      }
-    }
-    // coarse sources (APR level l-1): each element covers 2 x 2 x 2 level-l
-    // cells, in up to four halo rows
-    for (uint32_t base = nsf + tid; base < ns; base += NT * kBatch) {
-      int ss[kBatch], yv[kBatch], yn[kBatch];
-      uint32_t ii[kBatch], jj[kBatch];
-      PT val[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const uint32_t it = base + u * NT;
-        const bool ok = it < ns;
-        ss[u] = ok ? find_row(spre, NSRC, it) : 2 * NH;
-        jj[u] = ok ? it - spre[ss[u]] : 0u;
-        ii[u] = sp[ss[u]] + jj[u];
-        yv[u] = ok ? int(py[ii[u]]) : kBig;
-        const bool has_next = ok && jj[u] + 1 < spre[ss[u] + 1] - spre[ss[u]];
-        yn[u] = has_next ? int(py[ii[u] + 1]) : kBig;
-        if constexpr (INDEX)
-          val[u] = PT((int64_t(2) << 40) | int64_t(ii[u]));
-        else
-          val[u] = ok ? to_f32<TX>(xv[ii[u]]) : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        if (base + u * NT >= ns) continue;
-        const int s = ss[u];
-        const int lo = 2 * yv[u];
-        const int js = s - 2 * NH;
-        const int msk = cmask[js], hb = cbase[js];
-        const bool w0 = lo >= wlo && lo <= whi;
-        const bool w1 = lo + 1 >= wlo && lo + 1 <= whi && lo + 1 < Dy;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (!((msk >> q) & 1)) continue;
-          PT* row = patch + (hb + (q >> 1) * HX + (q & 1)) * PY - wlo;
-          if (w0) row[lo] = val[u];
-          if (w1) row[lo + 1] = val[u];
-        }
-        if (lo + 1 < drop && !(2 * yn[u] + 1 < drop)) scons[s] = jj[u] + 1;
-      }
-    }
-    lds_barrier();
+    if (tid == 0) s_cnt[par ^ 1] = 0;   // read last in the previous window's tap phase
+    const uint32_t nb = s_cnt[par];
+    wcur = wnext;
 
-    // ---- D: accumulate the taps of every listed particle
-    for (int s = tid; s < NSRC; s += NT) {
-      sp[s] += scons[s];
-      scons[s] = 0;
-    }
-    if (tid == 0) s_y0 = ynx;
-    if (tid < NC) {   // every wave has read them before the last barrier
-      rymax[tid] = -1;
-      rnext[tid] = int(kNoY);
-    }
+    // ---- taps of every listed output
     for (uint32_t jt = tid; jt < nb; jt += NT) {
       const int pos = o_pos[jt];
-      if (pos == kUnlisted) continue;
-      const int c = pos >> 6, p0 = (pos & 63) + R;
-      const uint32_t idx = opd[c] + (jt - ocap[c]);
-      const int hz = c / TX_, hx = c % TX_;   // halo row of the tap (-R, -R) is (hz, hx)
+      const uint32_t idx = o_idx[jt];
+      const int c = pos >> 6, p0 = pos & 63;
+      const int hz = c / TXr, hx = c % TXr;   // halo row of the tap (-R, -R) is (hz, hx)
+      const PT* pb = patch + (hz * HX + hx) * PY + p0;
       if constexpr (INDEX) {
         if (a.map32) {
           // tap-major layout [k^3][N_p]: consecutive particles are adjacent
@@ -411,7 +396,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
           for (int dz = 0; dz < K; ++dz)
             for (int dx = 0; dx < K; ++dx)
               for (int dy = 0; dy < K; ++dy) {
-                const int64_t code = int64_t(patch[((hz + dz) * HX + hx + dx) * PY + p0 - R + dy]);
+                const int64_t code = int64_t(pb[(dz * HX + dx) * PY + dy]);
                 a.map32[size_t(q++) * size_t(a.n_sel) + idx] =
                     code < 0 ? -1 : int32_t(((code >> 40) << 30) | (code & ((int64_t(1) << 30) - 1)));
               }
@@ -427,17 +412,16 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
           int q = 0;
           for (int dz = 0; dz < K; ++dz)
             for (int dx = 0; dx < K; ++dx)
-              for (int dy = 0; dy < K; ++dy)
-                dst[q++] = int64_t(patch[((hz + dz) * HX + hx + dx) * PY + p0 - R + dy]);
+              for (int dy = 0; dy < K; ++dy) dst[q++] = int64_t(pb[(dz * HX + dx) * PY + dy]);
         }
       } else if constexpr (NF == 3) {
         float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-#pragma unroll 1
+#pragma unroll
         for (int dz = 0; dz < K; ++dz) {
           cfloat* wz = wl + dz * K * K;
 #pragma unroll
           for (int dx = 0; dx < K; ++dx) {
-            const float* row = &patch[((hz + dz) * HX + hx + dx) * PY + p0 - R];
+            const float* row = pb + (dz * HX + dx) * PY;
 #pragma unroll
             for (int dy = 0; dy < K; ++dy) {
               const float v = row[dy];
@@ -450,12 +434,12 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
         static_cast<TY*>(a.y)[idx] = from_f32<TY>(sqrtf(fmaf(g0, g0, fmaf(g1, g1, g2 * g2))));
       } else {
         float acc = 0.f;
-#pragma unroll 1
+#pragma unroll
         for (int dz = 0; dz < K; ++dz) {
           cfloat* wz = wl + dz * K * K;
 #pragma unroll
           for (int dx = 0; dx < K; ++dx) {
-            const float* row = &patch[((hz + dz) * HX + hx + dx) * PY + p0 - R];
+            const float* row = pb + (dz * HX + dx) * PY;
 #pragma unroll
             for (int dy = 0; dy < K; ++dy) acc = fmaf(wz[dx * K + dy], row[dy], acc);
           }
@@ -476,6 +460,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 4 : ConvShape<K>::kWavesPerSimd))) vo
     par ^= 1;
   }
 }
+
 
 template <int K, bool INDEX>
 static apr_status launch_conv(const ConvArgs& args, int xdt, int ydt, hipStream_t s) {
@@ -515,6 +500,8 @@ static ConvArgs base_args(const apr_handle* h) {
   a.ty = h->ty;
   a.tend = h->tend;
   a.tiles = h->tiles;
+  a.wins = h->wins;
+  a.win_off = h->win_off;
   a.n_tiles = h->n_tiles;
   for (int x = 0; x <= 8; ++x) a.xcd_off[x] = h->xcd_off[x];
   a.n_wlevels = 1;
@@ -600,3 +587,4 @@ apr_status build_gather_map(const apr_handle* h, int k, int32_t* map32, hipStrea
   return k == 3 ? launch_conv<3, true>(a, APR_F32, APR_F32, s) : launch_conv<5, true>(a, APR_F32, APR_F32, s);
 }
 }  // namespace apr
+
