@@ -345,6 +345,60 @@ apr_status apr_level_weights(int32_t dir, const float* in, float* out, int64_t p
                              int32_t l_min, int32_t l_max, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
+/* ---- APR construction on the device (Section 2.3) ------------------------
+ * Builds the APR of a synthetic sphere-field image on the GPU: the particle
+ * LinearAccess (Algorithm 1) and the particle values.
+ *  - Level rule: a location at distance d from the nearest sphere surface
+ *    asks for level l_max - floor(log2(1 + d/2)); a cell of side
+ *    s = 2^(l_max - l) pixels is split when some point of the box spanned by
+ *    its pixel centres lies at d < 2 (s - 1).  (The paper derives the level
+ *    function from the image gradient and its local error scale; this rule
+ *    stands in for it on the synthetic inputs.)
+ *  - The Pulling Scheme's partition: from fine to coarse, the parent of every
+ *    cell touching (26-neighbourhood) a split cell of its level is split, so
+ *    neighbouring particle levels differ by at most one (Section 5.1); the
+ *    particles are the unsplit cells under split parents (all of level
+ *    l_min exist).
+ *  - Values: average downsampling (Section 2.3) of the image
+ *    clean = background + (foreground - background) (G * 1_union), G the
+ *    normalised Gaussian of edge_sigma pixels truncated at 4 sigma (zeros
+ *    outside the image; edge_sigma 0 = no blur), a pixel inside a sphere when
+ *    its centre is within the radius.  With `noise`, the sum S over a cell of
+ *    n pixels becomes S + sqrt(S) Z (the Gaussian limit of the Poisson law of
+ *    S), Z = (sum of 12 uniforms) - 6 from Philox4x64-10 with counter
+ *    (level << 48 | z << 32 | x << 16 | y, block 0..2, 0, 0) and key
+ *    (seed, 0), each uniform (word >> 11) * 2^-53; value = sum / n.
+ * Distance and inside tests are FP64 in a fixed order; blur and sums FP64
+ * accumulation (the image itself is FP32).  Synchronizes `stream`.  Device
+ * scratch: about 8 bytes per pixel during the call.
+ * Errors: APR_EINVAL (dims, l_min, sphere list), APR_EUNSUPPORTED (y size
+ * above 65535, 2^32 or more words of level bitmaps), APR_ENOMEM. */
+typedef struct {
+  int32_t dims[3];          /* image (N_z, N_x, N_y) */
+  int32_t l_min;            /* coarsest particle level */
+  int64_t n_spheres;
+  const double* centres;    /* host [n_spheres][3], (z, x, y) in pixel units (pixel p spans [p, p+1)) */
+  const double* radii;      /* host [n_spheres] */
+  double background, foreground, edge_sigma;
+  int32_t noise;            /* 1: cell noise as above */
+  uint64_t seed;
+} apr_sphere_field_desc;
+
+typedef struct apr_field apr_field;   /* the built APR; owns its device arrays */
+
+typedef struct {
+  int32_t dims[3];
+  int32_t l_min, l_max;
+  int64_t n_particles, n_rows;
+  const uint16_t* y_idx;    /* device [n_particles], Algorithm 1's y */
+  const uint64_t* xz_end;   /* device [n_rows], inclusive row ends (rows l -> z -> x) */
+  const float* values;      /* device [n_particles] */
+} apr_field_info;
+
+apr_status apr_sphere_field(const apr_sphere_field_desc* desc, void* stream, apr_field** out);
+apr_status apr_field_get_info(const apr_field* f, apr_field_info* out);
+apr_status apr_field_destroy(apr_field* f);   /* frees the field's device arrays */
+
 const char* apr_last_error(void);
 
 #ifdef __cplusplus

@@ -30,6 +30,7 @@ EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree",
             "apr_conv_bwd_data",
             "apr_conv_bwd_weight_ws", "apr_conv_bwd_weight", "apr_nn_workspace", "apr_moments",
             "apr_pointwise", "apr_relu_bias_grad", "apr_rel_l2", "apr_adam", "apr_level_weights",
+            "apr_sphere_field", "apr_field_get_info", "apr_field_destroy",
             "apr_last_error"]
 _SIZE_RETURNING = ("apr_richardson_lucy_workspace", "apr_conv_bwd_weight_ws", "apr_nn_workspace")
 
@@ -55,6 +56,18 @@ class ConvDesc(ctypes.Structure):
                 ("x_dtype", c_int32), ("y_dtype", c_int32), ("epilogue", c_int32), ("eps", c_float),
                 ("epi_arg", c_void_p), ("bias", c_void_p), ("relu", c_int32), ("residual", c_void_p),
                 ("power", c_float)]
+
+
+class SphereFieldDesc(ctypes.Structure):
+    _fields_ = [("dims", c_int32 * 3), ("l_min", c_int32), ("n_spheres", c_int64),
+                ("centres", c_void_p), ("radii", c_void_p), ("background", c_double),
+                ("foreground", c_double), ("edge_sigma", c_double), ("noise", c_int32), ("seed", c_uint64)]
+
+
+class FieldInfo(ctypes.Structure):
+    _fields_ = [("dims", c_int32 * 3), ("l_min", c_int32), ("l_max", c_int32),
+                ("n_particles", c_int64), ("n_rows", c_int64), ("y_idx", c_void_p), ("xz_end", c_void_p),
+                ("values", c_void_p)]
 
 
 class AprError(RuntimeError):
@@ -108,6 +121,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                              c_float, c_int32, c_void_p]
     lib.apr_level_weights.argtypes = [c_int32, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32,
                                       c_void_p]
+    lib.apr_sphere_field.argtypes = [POINTER(SphereFieldDesc), c_void_p, POINTER(c_void_p)]
+    lib.apr_field_get_info.argtypes = [c_void_p, POINTER(FieldInfo)]
+    lib.apr_field_destroy.argtypes = [c_void_p]
     lib.apr_last_error.argtypes = []
     lib.apr_last_error.restype = c_char_p
     for name in EXPORTED:

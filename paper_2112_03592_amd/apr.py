@@ -386,3 +386,54 @@ def fold_level_weights(G: torch.Tensor, n_sets: int, l_min: int, l_max: int) -> 
     L.check(L.load().apr_level_weights(1, _ptr(_f32(G)), _ptr(out), G[0].numel(), n_sets, l_min, l_max,
                                        _stream()))
     return out
+
+
+class _DeviceArray:
+    """A device array handed out by the library, seen by torch through the
+    CUDA array interface (no copy)."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 3}
+
+
+class DeviceField:
+    """An APR built on the device by ``apr_sphere_field``: the LinearAccess
+    copied to the host (numpy; ``AprAccess.from_input`` takes it) and the
+    particle values as a device tensor."""
+
+    def __init__(self, dims, l_min, l_max, y_idx, xz_end, values):
+        self.dims, self.l_min, self.l_max = tuple(dims), int(l_min), int(l_max)
+        self.y_idx, self.xz_end, self.values = y_idx, xz_end, values
+        self.n_particles = int(values.numel())
+
+
+def sphere_field(dims, l_min: int, centres, radii, background: float = 100.0, foreground: float = 1000.0,
+                 edge_sigma: float = 1.0, noise: bool = True, seed: int = 0) -> DeviceField:
+    """APR of a synthetic sphere field built on the device (``apr_sphere_field``)."""
+    lib = L.load()
+    c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    if c.shape[0] != r.shape[0]:
+        raise ValueError("one radius per centre")
+    d = L.SphereFieldDesc()
+    d.dims[:] = [int(v) for v in dims]
+    d.l_min = int(l_min)
+    d.n_spheres = r.size
+    d.centres = c.ctypes.data if r.size else None
+    d.radii = r.ctypes.data if r.size else None
+    d.background, d.foreground, d.edge_sigma = float(background), float(foreground), float(edge_sigma)
+    d.noise = 1 if noise else 0
+    d.seed = int(seed)
+    h = ctypes.c_void_p()
+    L.check(lib.apr_sphere_field(ctypes.byref(d), _stream(), ctypes.byref(h)))
+    try:
+        info = L.FieldInfo()
+        L.check(lib.apr_field_get_info(h, ctypes.byref(info)))
+        n, rows = int(info.n_particles), int(info.n_rows)
+        y = torch.as_tensor(_DeviceArray(info.y_idx, n, "<i2"), device="cuda").cpu().numpy().view(np.uint16)
+        e = torch.as_tensor(_DeviceArray(info.xz_end, rows, "<i8"), device="cuda").cpu().numpy().view(np.uint64)
+        v = torch.as_tensor(_DeviceArray(info.values, n, "<f4"), device="cuda").clone()
+        torch.cuda.current_stream().synchronize()
+    finally:
+        L.check(lib.apr_field_destroy(h))
+    return DeviceField(tuple(int(a) for a in info.dims), info.l_min, info.l_max, y, e, v)
