@@ -134,6 +134,17 @@ apr_status apr_access_export_tree(const apr_handle* h, uint16_t* tree_y_idx, uin
 apr_status apr_access_export(const apr_handle* h, int32_t which, void* a, void* b);
 
 /* Release the handle and its device memory. NULL is accepted. */
+/* The non-empty-tile pre-pass of Section 5.2 on its own (apr_access_build
+ * already ran it and keeps its result): for every candidate tile t of
+ * 8 x 8 particle rows at one level (finest level first, then z, x),
+ * flags[t] = 1 if one of its rows holds a particle, else 0, and ymin[t] =
+ * the smallest y of those particles (0xffff if none).  For timing the paper's
+ * pipeline (pre-pass + tree fill + convolution).  flags and ymin: device
+ * uint32 [apr_tile_prepass_size(h)], caller-owned.  Asynchronous on stream.
+ * Errors: APR_EINVAL (null handle or buffer). */
+int64_t apr_tile_prepass_size(const apr_handle* h);
+apr_status apr_tile_prepass(const apr_handle* h, uint32_t* flags, uint32_t* ymin, void* stream);
+
 apr_status apr_access_destroy(apr_handle* h);
 
 /* ----------------------------------------------------------------------

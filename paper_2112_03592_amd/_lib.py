@@ -31,8 +31,10 @@ EXPORTED = ["apr_access_build", "apr_access_get_info", "apr_access_export_tree",
             "apr_conv_bwd_weight_ws", "apr_conv_bwd_weight", "apr_nn_workspace", "apr_moments",
             "apr_pointwise", "apr_relu_bias_grad", "apr_rel_l2", "apr_adam", "apr_level_weights",
             "apr_sphere_field", "apr_field_get_info", "apr_field_destroy",
+            "apr_tile_prepass_size", "apr_tile_prepass",
             "apr_last_error"]
-_SIZE_RETURNING = ("apr_richardson_lucy_workspace", "apr_conv_bwd_weight_ws", "apr_nn_workspace")
+_SIZE_RETURNING = ("apr_richardson_lucy_workspace", "apr_conv_bwd_weight_ws", "apr_nn_workspace",
+                   "apr_tile_prepass_size")
 
 
 class AccessDesc(ctypes.Structure):
@@ -124,6 +126,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.apr_sphere_field.argtypes = [POINTER(SphereFieldDesc), c_void_p, POINTER(c_void_p)]
     lib.apr_field_get_info.argtypes = [c_void_p, POINTER(FieldInfo)]
     lib.apr_field_destroy.argtypes = [c_void_p]
+    lib.apr_tile_prepass_size.argtypes = [c_void_p]
+    lib.apr_tile_prepass_size.restype = c_int64
+    lib.apr_tile_prepass.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     lib.apr_last_error.argtypes = []
     lib.apr_last_error.restype = c_char_p
     for name in EXPORTED:

@@ -143,6 +143,19 @@ def fill_tree(acc: AprAccess, x: torch.Tensor, tree: Optional[torch.Tensor] = No
     return tree
 
 
+def tile_prepass(acc: AprAccess, flags: Optional[torch.Tensor] = None, ymin: Optional[torch.Tensor] = None):
+    """The Section 5.2 pre-pass on its own (``apr_tile_prepass``): per
+    candidate tile, occupied flag and smallest particle y."""
+    lib = L.load()
+    n = int(lib.apr_tile_prepass_size(acc.handle))
+    if flags is None:
+        flags = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    if ymin is None:
+        ymin = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    L.check(lib.apr_tile_prepass(acc.handle, _ptr(flags), _ptr(ymin), _stream()))
+    return flags[:n], ymin[:n]
+
+
 def stencil_levels(w, mode: str, k: int, l_min: int, l_max: int, flip: bool = False) -> np.ndarray:
     """Per-level stencils [l_max-l_min+1, *lead, k, k, k] (FP32) computed by
     ``apr_stencil_levels`` from w [*lead, k, k, k]."""

@@ -282,6 +282,21 @@ __device__ inline void tile_locate(const TileLevels& tl, int64_t t, int& l, int&
   tx = int(r % tl.ntx[j]);
 }
 
+// candidate tiles of every level, finest level first
+static TileLevels tile_levels(const Meta& m) {
+  TileLevels tl{};
+  int64_t ntot = 0;
+  for (int l = m.l_max; l >= m.l_min; --l) {
+    const int j = tl.n_levels++;
+    tl.level[j] = l;
+    tl.first[j] = ntot;
+    tl.ntx[j] = (m.dx[l] + kTileX - 1) / kTileX;
+    ntot += int64_t((m.dz[l] + kTileZ - 1) / kTileZ) * tl.ntx[j];
+  }
+  tl.first[tl.n_levels] = ntot;
+  return tl;
+}
+
 // flags[t] = tile t holds particles; ymin[t] = smallest y among them
 __global__ void tile_flag_kernel(Meta m, TileLevels tl, const uint32_t* __restrict__ pend,
                                  const uint16_t* __restrict__ py, uint32_t* flags, uint32_t* ymin, int64_t n) {
@@ -655,16 +670,8 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
 
   // ---- tile list
   {
-    TileLevels tl{};
-    int64_t ntot = 0;
-    for (int l = lmax; l >= d->l_min; --l) {
-      const int j = tl.n_levels++;
-      tl.level[j] = l;
-      tl.first[j] = ntot;
-      tl.ntx[j] = (m.dx[l] + kTileX - 1) / kTileX;
-      ntot += int64_t((m.dz[l] + kTileZ - 1) / kTileZ) * tl.ntx[j];
-    }
-    tl.first[tl.n_levels] = ntot;
+    const TileLevels tl = tile_levels(m);
+    const int64_t ntot = tl.first[tl.n_levels];
     void* q = nullptr;
     APR_TRY_HIP(hipMalloc(&q, size_t(ntot + 1) * 4));
     tmp.push_back(q);
@@ -807,6 +814,24 @@ apr_status apr_access_export(const apr_handle* h, int32_t which, void* a, void* 
     default:
       APR_FAIL(APR_EINVAL, "apr_access_export: which must be APR_EXPORT_APR, APR_EXPORT_TREE or APR_EXPORT_TILES");
   }
+}
+
+int64_t apr_tile_prepass_size(const apr_handle* h) {
+  if (!h) return 0;
+  const TileLevels tl = tile_levels(h->meta);
+  return tl.first[tl.n_levels];
+}
+
+apr_status apr_tile_prepass(const apr_handle* h, uint32_t* flags, uint32_t* ymin, void* stream) {
+  if (!h) APR_FAIL(APR_EINVAL, "apr_tile_prepass: null handle");
+  const TileLevels tl = tile_levels(h->meta);
+  const int64_t n = tl.first[tl.n_levels];
+  if (n == 0) return APR_OK;
+  if (!flags || !ymin) APR_FAIL(APR_EINVAL, "apr_tile_prepass: null buffer");
+  hipLaunchKernelGGL(tile_flag_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), h->meta, tl, h->pend, h->py, flags, ymin, n);
+  APR_HIP(hipGetLastError());
+  return APR_OK;
 }
 
 apr_status apr_access_destroy(apr_handle* h) {

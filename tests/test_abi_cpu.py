@@ -20,7 +20,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="libaprco
 
 def declared_functions():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:apr_status|const char\*|size_t)\s+(apr_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:apr_status|const char\*|size_t|int64_t)\s+(apr_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_declares_the_boundary():

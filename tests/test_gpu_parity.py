@@ -79,6 +79,21 @@ def test_export_apr_and_tiles(name):
     assert len(got) == tiles.shape[0], "a tile is listed twice"
     assert got == want
     assert off[0] == 0 and off[8] == tiles.shape[0] and np.all(np.diff(off) >= 0)
+    # the pre-pass on its own: one flag and smallest y per candidate tile,
+    # finest level first, then tile z, tile x
+    with G.AprAccess.from_input(inp) as acc:
+        flags, ymin = G.tile_prepass(acc)
+        flags, ymin = flags.cpu().numpy(), ymin.cpu().numpy()
+    k = 0
+    for l in range(la.l_max, la.l_min - 1, -1):
+        dz, dx = la.z_dim[l], la.x_dim[l]
+        for tz in range(-(-dz // 8)):
+            for tx in range(-(-dx // 8)):
+                key = (l, tz, tx)
+                assert flags[k] == (key in want), key
+                assert ymin[k] == want.get(key, 0xffff), key
+                k += 1
+    assert k == flags.shape[0]
 
 
 @pytest.mark.parametrize("name", list(SMALL_CASES))
