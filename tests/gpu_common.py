@@ -46,3 +46,38 @@ def assert_close_scaled(got: np.ndarray, ref: np.ndarray, scale: np.ndarray, tol
         raise AssertionError(f"{what}: {int(bad.sum())} of {got.size} outside {tol} x scale; worst at {i}: "
                              f"got {got.flat[i]!r} ref {ref.flat[i]!r} scale {scale.flat[i]!r}")
     return float((err / np.maximum(scale, 1e-300)).max()) if err.size else 0.0
+
+
+def corner_block(dims, lmax_img: int, l_first: int, l_last: int, y_idx, xz_end, edge: int):
+    """The cells of levels l_first..l_last (image finest level lmax_img) that
+    lie in the corner cube [0, edge)^3, encoded as a LinearAccess of that cube
+    (its levels shift down by lmax_img - log2(edge)); ``edge`` is a multiple
+    of the coarsest cell, so no cell straddles the cube.  Returns
+    (y_idx, xz_end, index of each kept element in the input arrays)."""
+    y_all = np.asarray(y_idx)
+    e_all = np.asarray(xz_end).astype(np.int64)
+    ys, cnts, idxs = [], [], []
+    row0 = 0
+    for l in range(l_first, l_last + 1):
+        s = 1 << (lmax_img - l)
+        assert edge % s == 0
+        dz, dx = -(-dims[0] // s), -(-dims[1] // s)
+        lim = edge // s
+        zz, xx = np.meshgrid(np.arange(min(lim, dz)), np.arange(min(lim, dx)), indexing="ij")
+        rows = row0 + zz.ravel() * dx + xx.ravel()
+        e = e_all[rows]
+        b = np.where(rows > 0, e_all[np.maximum(rows - 1, 0)], 0)
+        n = e - b
+        first = np.repeat(b - np.concatenate([[0], np.cumsum(n)[:-1]]), n)
+        idx = first + np.arange(int(n.sum()))
+        y = y_all[idx]
+        keep = y < lim
+        rid = np.repeat(np.arange(rows.size), n)
+        cnt = np.zeros((lim, lim), np.int64)
+        cnt[:zz.shape[0], :zz.shape[1]] = np.bincount(rid[keep], minlength=rows.size).reshape(zz.shape)
+        cnts.append(cnt.ravel())
+        ys.append(y[keep])
+        idxs.append(idx[keep])
+        row0 += dz * dx
+    return (np.concatenate(ys).astype(np.int64), np.cumsum(np.concatenate(cnts)).astype(np.int64),
+            np.concatenate(idxs).astype(np.int64))
