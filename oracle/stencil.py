@@ -54,14 +54,8 @@ def restrict_stencil(w: np.ndarray, s: int) -> np.ndarray:
     if s == 1:
         return w.copy()
     n = _axis_counts(s, r)
-    out = np.zeros_like(w)
-    for t in itertools.product(range(-r, r + 1), repeat=3):
-        wt = w[(...,) + tuple(ti + r for ti in t)]
-        for J in itertools.product(range(-r, r + 1), repeat=3):
-            c = n[J[0] + r, t[0] + r] * n[J[1] + r, t[1] + r] * n[J[2] + r, t[2] + r]
-            if c:
-                out[(...,) + tuple(j + r for j in J)] += wt * (c / s ** 3)
-    return out
+    # sum over t of w[t] times the product of the per-axis counts
+    return np.einsum("ai,bj,ck,...ijk->...abc", n, n, n, w) / float(s) ** 3
 
 
 def restrict_stencil_enumerated(w: np.ndarray, s: int) -> np.ndarray:

@@ -33,7 +33,8 @@ def test_golden_tiny4_outputs():
     assert ys[:, 0].tolist() == list(g["ones3_outputs"].values())
 
 
-@pytest.mark.parametrize("dims,k,seed", [((5, 6, 7), 3, 0), ((8, 4, 9), 5, 1), ((16, 16, 16), 3, 2), ((6, 6, 6), 5, 3)])
+@pytest.mark.parametrize("dims,k,seed", [((5, 6, 7), 3, 0), ((8, 4, 9), 5, 1), ((16, 16, 16), 3, 2), ((6, 6, 6), 5, 3),
+                                         ((11, 9, 14), 7, 4), ((10, 13, 8), 9, 5), ((9, 17, 15), 13, 6)])
 def test_all_finest_equals_pixel_correlation(dims, k, seed):
     """Section 4.1: at the finest level APR convolution is convolution of the
     reconstructed image.  An asymmetric stencil pins orientation
@@ -310,3 +311,53 @@ def test_rl_power_all_finest_equals_pixel_recursion():
         rho = u / np.maximum(ndimage.convolve(i, psf, mode="constant", cval=0.0), eps)
         i = i * ndimage.correlate(rho, psf, mode="constant", cval=0.0) ** 2.2
     assert np.allclose(got, i.reshape(-1), rtol=1e-11)
+
+
+@pytest.mark.parametrize("k,seed,sep", [(7, 0, True), (9, 1, False), (13, 2, True), (13, 3, False)])
+def test_large_stencils_are_level_wise_correlations(k, seed, sep):
+    """Stencils above 5^3 (the line / plane decomposition of Section 7): on
+    every level l, the convolution of the level-l particles equals the
+    correlation of the dense level-l reconstruction V_l (Section 3.5; taps now
+    reach particles two levels coarser) with w_l, sampled at the particles.
+    For a separable stencil the reference is computed line by line (three 1-D
+    passes), otherwise plane by plane."""
+    rng = np.random.default_rng(seed)
+    inp = random_apr((30, 26, 34), l_min=0, seed=(41, 42, 43, 45)[seed], p_refine=0.2)
+    la = _la(inp)
+    tr = A.tree_structure(la)
+    x = inp.values.astype(np.float64)
+    if sep:
+        g = [rng.uniform(0.1, 1.0, k) for _ in range(3)]
+        w = g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :]
+    else:
+        w = rng.normal(size=(k, k, k))
+    wl = level_stencils(w, RESTRICT, la.l_min, la.l_max)
+    y = np.asarray(C.apr_conv(la, x, wl, tree=tr)).reshape(-1)
+    t2 = fill_tree(la, tr, x[:, None])
+    for l in range(la.l_min, la.l_max + 1):
+        b, e = la.level_range(l)
+        if e == b:
+            continue
+        V = C.level_grid(la, tr, x[:, None], t2, l)[..., 0]
+        W = wl[l - la.l_min]
+        if sep:
+            # w_l = restrict(outer product) stays an outer product: recover its factors
+            i = np.unravel_index(np.argmax(np.abs(W)), W.shape)
+            fz, fx, fy = W[:, i[1], i[2]], W[i[0], :, i[2]], W[i[0], i[1], :]
+            ref = ndimage.correlate1d(V, fz, axis=0, mode="constant")
+            ref = ndimage.correlate1d(ref, fx / fx[i[1]], axis=1, mode="constant")
+            ref = ndimage.correlate1d(ref, fy / fy[i[2]], axis=2, mode="constant")
+        else:
+            r = k // 2
+            ref = np.zeros_like(V)
+            for dz in range(-r, r + 1):
+                plane = ndimage.correlate(V, W[dz + r][None], mode="constant")
+                src = slice(max(0, dz), V.shape[0] + min(0, dz))
+                dst = slice(max(0, -dz), V.shape[0] - max(0, dz))
+                ref[dst] += plane[src]
+        c = la.cells(l)
+        want = ref[c[:, 0], c[:, 1], c[:, 2]]
+        assert np.allclose(y[b:e], want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+    if k >= 9:
+        src, _ = C.neighbor_map(la, k, np.arange(la.n), tree=tr)
+        assert (src == C.SRC_FAR).any(), "no tap reached a particle two levels coarser"
