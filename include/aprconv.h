@@ -173,7 +173,7 @@ apr_status apr_fill_tree(const apr_handle* h, const void* x, void* tree, int32_t
 /* Host helper, FP64 arithmetic, FP32 output.  w: host [n_filters][k^3]
  * (n_filters = C_out*C_in); out: host [l_max-l_min+1][n_filters][k^3].
  * flip != 0 reverses w in every dimension first (the flipped PSF of
- * Section 6.2).  k in {3, 5}. */
+ * Section 6.2).  k odd, 3 to 13 (APR_EUNSUPPORTED otherwise). */
 apr_status apr_stencil_levels(int32_t mode, int32_t k, int32_t n_filters, const double* w,
                               int32_t l_min, int32_t l_max, int32_t flip, float* out);
 
@@ -191,7 +191,7 @@ apr_status apr_stencil_levels(int32_t mode, int32_t k, int32_t n_filters, const 
                              w is [n_wlevels][3][k^3], x F32 or BF16, y F32 */
 
 typedef struct {
-  int32_t k;             /* stencil side: 3 or 5 */
+  int32_t k;             /* stencil side: 3 or 5; single channel also 7, 9, 11, 13 */
   int32_t c_in, c_out;   /* channels (this build: 1 and 1) */
   int32_t n_wlevels;     /* 1 (one stencil for every level) or l_max-l_min+1 */
   int32_t x_dtype;       /* APR_F32 / APR_BF16 / APR_FP8: storage of x and tree */
@@ -209,7 +209,12 @@ typedef struct {
  * the level-l reconstruction (Section 3.5): the value of the particle at a
  * level <= l containing the cell, else the tree value of the cell, 0 outside
  * the image.  Requires a balanced APR (neighbouring levels differ by <= 1),
- * so every tap is supplied by APR level l, APR level l-1 or tree level l.
+ * so every tap of a stencil up to 5^3 is supplied by APR level l, APR level
+ * l-1 or tree level l, and every tap up to 13^3 also by APR level l-2 (a
+ * level-(l-j) particle lies at least 2^j - 1 level-l cells away).  Stencils
+ * above 5^3 (Section 7's extension; single channel, FP32 x and y, any
+ * epilogue but APR_EPI_GRADMAG) sum the k^2 lines of the stencil from
+ * patches of at most 16 output cells along y.
  * x: device [N_p][c_in]; tree: device [N_t][c_in], filled from this exact x
  * by apr_fill_tree (not checked); w: device FP32 weights; y: device
  * [N_p][c_out], must not alias x or tree.  Asynchronous. */

@@ -31,13 +31,21 @@ namespace apr {
 
 constexpr int kBig = 1 << 28;    // key of a missing element
 // Launch shape per stencil size.  Source rows are served by groups of kG
-// lanes; each group moves kG * kNB elements of its row per memory round.
+// lanes; each group moves kG * kNB elements of its row per memory round.  A
+// patch holds output y spans of at most kW cells.  Within radius r of a
+// level-l particle, 26-neighbour 2:1 balance admits particles of level l - j
+// only at distances of at least 2^j - 1 cells, so stencils up to 5^3 read APR
+// levels l and l-1 (and tree level l), stencils up to 13^3 also level l-2.
 template <int K>
 struct ConvShape {
-  static constexpr int kThreads = 768;
+  static_assert(K % 2 == 1 && K >= 3 && K <= 13, "odd stencil sides 3..13");
+  static constexpr bool kLarge = K > 5;
+  static constexpr int kThreads = kLarge ? 1024 : 768;
   static constexpr int kG = 8;
-  static constexpr int kNB = 2;
-  static constexpr int kWavesPerSimd = 6;
+  static constexpr int kNB = kLarge ? 1 : 2;
+  static constexpr int kWavesPerSimd = kLarge ? 4 : 6;
+  static constexpr int kW = kLarge ? 16 : kWinY;
+  static constexpr int kDepth = kLarge ? 2 : 1;   // coarsest APR source level: l - kDepth
 };
 
 struct ConvArgs {
@@ -87,23 +95,28 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   constexpr int TZ = kTileZ, TXr = kTileX;
   constexpr int HZ = TZ + 2 * R, HX = TXr + 2 * R;
   constexpr int NH = HZ * HX;                        // halo rows at level l
-  constexpr int PX = ((TXr - 1 + R) >> 1) + 2;       // parent rows (level l-1) per axis
-  constexpr int PZ = ((TZ - 1 + R) >> 1) + 2;
-  constexpr int NCR = PZ * PX;
-  constexpr int NSRC = 2 * NH + NCR;                 // [0,NH) APR l, [NH,2NH) tree l, rest APR l-1
+  constexpr int W = ConvShape<K>::kW, D = ConvShape<K>::kDepth;
+  // rows of APR level l-j covering the halo: per axis from tile origin / 2^j
+  // - CRj on (the tile origin is a multiple of 8)
+  constexpr int CR1 = (R + 1) / 2, CR2 = (R + 3) / 4;
+  constexpr int P1 = ((TXr - 1 + R) >> 1) + CR1 + 1;
+  constexpr int P2 = D >= 2 ? ((TXr - 1 + R) >> 2) + CR2 + 1 : 0;
+  constexpr int NCR1 = P1 * P1, NCR2 = P2 * P2;
+  // source rows: [0,NH) APR l, [NH,2NH) tree l, then APR l-1, then APR l-2
+  constexpr int NSRC = 2 * NH + NCR1 + NCR2;
   constexpr int RPG = (NSRC + NG - 1) / NG;          // source rows per group
   constexpr int NC = TZ * TXr;                       // centre (output) rows
-  constexpr int PY = kWinY + 2 * R;
+  constexpr int PY = W + 2 * R;
   constexpr int K3 = K * K * K;
   constexpr uint32_t kNone = 0xffffffffu;
   constexpr int kUnknown = -1;                       // y at the cursor not yet read
   using PT = typename std::conditional<INDEX, long long, float>::type;
-  static_assert(NC <= 64 && kWinY == 64, "output positions pack into 12 bits");
+  static_assert(NC <= 64 && W <= 64 && TZ == TXr, "output positions pack into 12 bits");
   static_assert(64 % G == 0 && GB <= 32, "lane groups tile a wave; batch masks are 32-bit");
 
   __shared__ PT patch[NH * PY];
-  __shared__ uint32_t o_idx[NC * kWinY];   // listed outputs of the window: particle index
-  __shared__ uint16_t o_pos[NC * kWinY];   // (centre row << 6) | (y - y0)
+  __shared__ uint32_t o_idx[NC * W];   // listed outputs of the patch: particle index
+  __shared__ uint16_t o_pos[NC * W];   // (centre row << 6) | (y - y0)
   __shared__ uint32_t s_cnt[2];            // outputs listed, per window parity
 
   const int tid = threadIdx.x;
@@ -127,7 +140,6 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   const Meta& m = a.m;
   const int z0 = tz * TZ, x0 = tx * TXr;
   const int Dz = m.dz[l], Dx = m.dx[l], Dy = m.dy[l];
-  const bool has_c = l > m.l_min;
   const bool has_t = l <= m.t_hi;
   const TX* __restrict__ xv = static_cast<const TX*>(a.x);
   const TX* __restrict__ tv = static_cast<const TX*>(a.tree);
@@ -156,11 +168,16 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
       const bool in = z >= 0 && x >= 0 && z < Dz && x < Dx;
       if (in && s < NH) row_range(a.pend, m.prow[l] + uint32_t(z) * Dx + x, b, e);
       if (in && s >= NH && has_t) row_range(a.tend, m.trow[l] + uint32_t(z) * Dx + x, b, e);
-    } else if (s < NSRC && has_c) {
-      const int j = s - 2 * NH;
-      const int pz = z0 / 2 - 1 + j / PX, px = x0 / 2 - 1 + j % PX;
-      if (pz >= 0 && px >= 0 && pz < m.dz[l - 1] && px < m.dx[l - 1])
-        row_range(a.pend, m.prow[l - 1] + uint32_t(pz) * m.dx[l - 1] + px, b, e);
+    } else if (s < NSRC) {
+      const int dep = s < 2 * NH + NCR1 ? 1 : 2;
+      const int j = dep == 1 ? s - 2 * NH : s - 2 * NH - NCR1;
+      const int P = dep == 1 ? P1 : P2, CR = dep == 1 ? CR1 : CR2;
+      const int lc = l - dep;
+      if (lc >= m.l_min) {
+        const int pz = (z0 >> dep) - CR + j / P, px = (x0 >> dep) - CR + j % P;
+        if (pz >= 0 && px >= 0 && pz < m.dz[lc] && px < m.dx[lc])
+          row_range(a.pend, m.prow[lc] + uint32_t(pz) * m.dx[lc] + px, b, e);
+      }
     }
     cur[r] = b;
     end[r] = e;
@@ -195,14 +212,26 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   if (tid < 2) s_cnt[tid] = 0;
   lds_barrier();
 
+  // patches: each window of the tile in spans of at most W output cells
   int par = 0;
+  uint32_t wi = w_beg;
   uint32_t wcur = a.wins[w_beg];
-  for (uint32_t wi = w_beg; wi < w_end; ++wi) {
-    const int y0 = int(wcur & 0xffffu), y1 = int(wcur >> 16);
+  int y0 = int(wcur & 0xffffu), y1 = min(int(wcur >> 16), y0 + W - 1);
+  while (true) {
     const int wlo = y0 - R, whi = y1 + R;
-    const bool has_next = wi + 1 < w_end;
-    const uint32_t wnext = has_next ? a.wins[wi + 1] : 0u;
-    const int nwlo = int(wnext & 0xffffu) - R, nwhi = int(wnext >> 16) + R;
+    int ny0 = 0, ny1 = -1;
+    bool has_next = true;
+    if (y1 < int(wcur >> 16)) {
+      ny0 = y1 + 1;
+      ny1 = min(int(wcur >> 16), ny0 + W - 1);
+    } else if (wi + 1 < w_end) {
+      const uint32_t wn = a.wins[wi + 1];
+      ny0 = int(wn & 0xffffu);
+      ny1 = min(int(wn >> 16), ny0 + W - 1);
+    } else {
+      has_next = false;
+    }
+    const int nwlo = ny0 - R, nwhi = ny1 + R;
 
     // ---- sources: every element of the group's rows that covers a cell of
     // [wlo, whi] is written into the level-l patch; centre-row particles in
@@ -211,8 +240,9 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
     for (int r = 0; r < RPG; ++r) {
       const int s = grp + r * NG;
       const uint32_t e = end[r];
-      const bool coarse = s >= 2 * NH;
-      const int sh = coarse ? 1 : 0;   // element y covers cells [y << sh, ((y + 1) << sh) - 1]
+      // element y covers cells [y << sh, ((y + 1) << sh) - 1]
+      const int sh = s < 2 * NH ? 0 : (D == 1 || s < 2 * NH + NCR1 ? 1 : 2);
+      const bool coarse = sh > 0;
       if (s < NSRC && act[r]) {         // uniform per group
         const bool istree = s >= NH && !coarse;
         const uint16_t* __restrict__ ys = istree ? ty : py;
@@ -220,16 +250,25 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
         const int h = s < NH ? s : s - NH;
         const bool centre = s < NH && h / HX >= R && h / HX < R + TZ && h % HX >= R && h % HX < R + TXr;
         const int c = (h / HX - R) * TXr + (h % HX - R);
-        // coarse row: its element covers 2 x 2 halo rows from hb (mask of the
-        // ones inside the halo and the level-l grid)
+        // coarse row: its element covers 2^sh x 2^sh halo rows from hb (mask
+        // of the ones inside the halo and the level-l grid)
         int hb = 0, msk = 0;
-        if (coarse) {
+        if (D == 1 && coarse) {
           const int j = s - 2 * NH;
-          const int hz0 = 2 * (j / PX) + R - 2, hx0 = 2 * (j % PX) + R - 2;
+          const int hz0 = 2 * (j / P1 - CR1) + R, hx0 = 2 * (j % P1 - CR1) + R;
           hb = hz0 * HX + hx0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int hz = hz0 + (q >> 1), hx = hx0 + (q & 1);
+            if (hz >= 0 && hx >= 0 && hz < HZ && hx < HX && z0 - R + hz < Dz && x0 - R + hx < Dx) msk |= 1 << q;
+          }
+        } else if (coarse) {
+          const int j = sh == 1 ? s - 2 * NH : s - 2 * NH - NCR1;
+          const int P = sh == 1 ? P1 : P2, CR = sh == 1 ? CR1 : CR2, n = 1 << sh;
+          const int hz0 = n * (j / P - CR) + R, hx0 = n * (j % P - CR) + R;
+          hb = hz0 * HX + hx0;
+          for (int q = 0; q < n * n; ++q) {
+            const int hz = hz0 + q / n, hx = hx0 + q % n;
             if (hz >= 0 && hx >= 0 && hz < HZ && hx < HX && z0 - R + hz < Dz && x0 - R + hx < Dx) msk |= 1 << q;
           }
         }
@@ -294,7 +333,7 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
             if (ok && (y << sh) <= whi && ((y + 1) << sh) - 1 >= wlo) {
               if (!coarse) {
                 patch[h * PY + (y - wlo)] = val[u];
-              } else {
+              } else if (D == 1 || sh == 1) {
                 const int c0 = 2 * y;
                 const bool w0 = c0 >= wlo, w1 = c0 + 1 <= whi && c0 + 1 < Dy;
 #pragma unroll
@@ -303,6 +342,17 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
                   PT* row = patch + (hb + (q >> 1) * HX + (q & 1)) * PY - wlo;
                   if (w0) row[c0] = val[u];
                   if (w1) row[c0 + 1] = val[u];
+                }
+              } else if constexpr (D >= 2) {
+                const int c0 = 4 * y;
+                for (int q = 0; q < 16; ++q) {
+                  if (!((msk >> q) & 1)) continue;
+                  PT* row = patch + (hb + (q >> 2) * HX + (q & 3)) * PY - wlo;
+#pragma unroll
+                  for (int tq = 0; tq < 4; ++tq) {
+                    const int cc = c0 + tq;
+                    if (cc >= wlo && cc <= whi && cc < Dy) row[cc] = val[u];
+                  }
                 }
               }
             }
@@ -380,7 +430,6 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
 
     if (tid == 0) s_cnt[par ^ 1] = 0;   // read last in the previous window's tap phase
     const uint32_t nb = s_cnt[par];
-    wcur = wnext;
 
     // ---- taps of every listed output
     for (uint32_t jt = tid; jt < nb; jt += NT) {
@@ -434,10 +483,10 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
         static_cast<TY*>(a.y)[idx] = from_f32<TY>(sqrtf(fmaf(g0, g0, fmaf(g1, g1, g2 * g2))));
       } else {
         float acc = 0.f;
-#pragma unroll
+#pragma unroll(K == 3 ? K : 1)
         for (int dz = 0; dz < K; ++dz) {
           cfloat* wz = wl + dz * K * K;
-#pragma unroll
+#pragma unroll(K <= 5 ? K : 1)
           for (int dx = 0; dx < K; ++dx) {
             const float* row = pb + (dz * HX + dx) * PY;
 #pragma unroll
@@ -457,6 +506,10 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
       }
     }
     lds_barrier();
+    if (!has_next) break;
+    if (y1 >= int(wcur >> 16)) wcur = a.wins[++wi];
+    y0 = ny0;
+    y1 = ny1;
     par ^= 1;
   }
 }
@@ -481,11 +534,14 @@ static apr_status launch_conv(const ConvArgs& args, int xdt, int ydt, hipStream_
   }
   if (xdt == APR_F32 && ydt == APR_F32)
     hipLaunchKernelGGL((conv1_kernel<K, float, float, INDEX>), grid, dim3(ConvShape<K>::kThreads), 0, s, args);
+  else if (K > 5)
+    APR_FAIL(APR_EUNSUPPORTED, "apr_conv: stencils above 5^3 take F32 values");
   else if (xdt == APR_BF16 && ydt == APR_BF16)
-    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, __hip_bfloat16, INDEX>), grid, dim3(ConvShape<K>::kThreads), 0,
-                       s, args);
+    hipLaunchKernelGGL((conv1_kernel<K <= 5 ? K : 3, __hip_bfloat16, __hip_bfloat16, INDEX>), grid,
+                       dim3(ConvShape<K>::kThreads), 0, s, args);
   else if (xdt == APR_BF16 && ydt == APR_F32)
-    hipLaunchKernelGGL((conv1_kernel<K, __hip_bfloat16, float, INDEX>), grid, dim3(ConvShape<K>::kThreads), 0, s, args);
+    hipLaunchKernelGGL((conv1_kernel<K <= 5 ? K : 3, __hip_bfloat16, float, INDEX>), grid,
+                       dim3(ConvShape<K>::kThreads), 0, s, args);
   else
     APR_FAIL(APR_EUNSUPPORTED, "apr_conv: unsupported dtype combination");
   APR_HIP(hipGetLastError());
@@ -528,7 +584,7 @@ apr_status apr::conv_impl(const apr_handle* h, const apr_conv_desc* d, const voi
                           const void* tree, const float* w, void* y, const float* eps_dev,
                           void* stream) {
   if (!h || !d) APR_FAIL(APR_EINVAL, "apr_conv: null handle or descriptor");
-  if (d->k != 3 && d->k != 5) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: k must be 3 or 5");
+  if (d->k < 3 || d->k > 13 || d->k % 2 == 0) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: k must be 3, 5, 7, 9, 11 or 13");
   if (d->c_in < 1 || d->c_out < 1) APR_FAIL(APR_EINVAL, "apr_conv: channel counts must be >= 1");
   const int nl = h->meta.l_max - h->meta.l_min + 1;
   if (d->n_wlevels != 1 && d->n_wlevels != nl)
@@ -542,6 +598,7 @@ apr_status apr::conv_impl(const apr_handle* h, const apr_conv_desc* d, const voi
   if (y == x || y == tree) APR_FAIL(APR_EINVAL, "apr_conv: y must not alias x or tree");
   if (d->c_in != 1 || d->c_out != 1 || d->bias || d->relu || d->residual) {
     if (d->epilogue != APR_EPI_NONE) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: epilogues need c_in = c_out = 1");
+    if (d->k > 5) APR_FAIL(APR_EUNSUPPORTED, "apr_conv: multichannel layers take k = 3 or 5");
     return mc_conv(h, d, x, tree, w, y, static_cast<hipStream_t>(stream));
   }
   ConvArgs a = base_args(h);
@@ -556,8 +613,14 @@ apr_status apr::conv_impl(const apr_handle* h, const apr_conv_desc* d, const voi
   a.power = d->power;
   a.epi_arg = d->epi_arg;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return d->k == 3 ? launch_conv<3, false>(a, d->x_dtype, d->y_dtype, s)
-                   : launch_conv<5, false>(a, d->x_dtype, d->y_dtype, s);
+  switch (d->k) {
+    case 3: return launch_conv<3, false>(a, d->x_dtype, d->y_dtype, s);
+    case 5: return launch_conv<5, false>(a, d->x_dtype, d->y_dtype, s);
+    case 7: return launch_conv<7, false>(a, d->x_dtype, d->y_dtype, s);
+    case 9: return launch_conv<9, false>(a, d->x_dtype, d->y_dtype, s);
+    case 11: return launch_conv<11, false>(a, d->x_dtype, d->y_dtype, s);
+    default: return launch_conv<13, false>(a, d->x_dtype, d->y_dtype, s);
+  }
 }
 
 extern "C" apr_status apr_neighbor_map(const apr_handle* h, int32_t k, const int64_t* particles,

@@ -42,7 +42,7 @@ static void apply_axis(int k, const std::vector<double>& M, int axis, const doub
 
 extern "C" apr_status apr_stencil_levels(int32_t mode, int32_t k, int32_t n_filters, const double* w,
                                          int32_t l_min, int32_t l_max, int32_t flip, float* out) {
-  if (k != 3 && k != 5) APR_FAIL(APR_EUNSUPPORTED, "apr_stencil_levels: k must be 3 or 5");
+  if (k < 3 || k > 13 || k % 2 == 0) APR_FAIL(APR_EUNSUPPORTED, "apr_stencil_levels: k must be odd, 3 to 13");
   if (n_filters < 1 || !w || !out) APR_FAIL(APR_EINVAL, "apr_stencil_levels: bad arguments");
   if (l_min < 0 || l_max < l_min || l_max >= kMaxL)
     APR_FAIL(APR_EINVAL, "apr_stencil_levels: bad level range");

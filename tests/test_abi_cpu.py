@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("mode,omode", [(0, SAME), (1, RESTRICT), (2, ADAPTIVE)])
-@pytest.mark.parametrize("k", [3, 5])
+@pytest.mark.parametrize("k", [3, 5, 7, 13])
 @pytest.mark.parametrize("do_flip", [0, 1])
 def test_stencil_levels_match_oracle(mode, omode, k, do_flip):
     from paper_2112_03592_amd.apr import stencil_levels

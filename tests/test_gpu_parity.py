@@ -136,6 +136,26 @@ def test_conv_fp32(name, k, mode):
     assert_close_scaled(y, ref, scale, 1e-5, f"{name} k={k} {mode}")
 
 
+@pytest.mark.parametrize("name", ["rand8_l0", "rand9x12x7", "rand33x20x70", "rand_long_y", "single_cell",
+                                  "dense13x11x70", "sphere64"])
+@pytest.mark.parametrize("k", [7, 9, 11, 13])
+@pytest.mark.parametrize("mode", ["restrict", "explicit"])
+def test_conv_large_stencils(name, k, mode):
+    """Stencils above 5^3: taps reach APR level l-2; patches of at most 16
+    output cells along y."""
+    say("conv large", name, k, mode)
+    inp, la, tr = case(name)
+    w32 = _weights(k, mode, la, seed=k)
+    x64 = inp.values.astype(np.float64)
+    ref = C.apr_conv(la, x64, w32.astype(np.float64), tree=tr)
+    scale = C.apr_conv(la, np.abs(x64), np.abs(w32.astype(np.float64)), tree=tr)
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(inp.values).cuda()
+        t = G.fill_tree(acc, x)
+        y = G.conv(acc, x, t, torch.from_numpy(np.ascontiguousarray(w32)).cuda(), k).cpu().numpy()
+    assert_close_scaled(y, ref, scale, 1e-5, f"{name} k={k} {mode}")
+
+
 @pytest.mark.parametrize("name", ["rand16_l1", "rand33x20x70", "sphere64"])
 def test_conv_shared_stencil_and_signed_values(name):
     inp, la, tr = case(name)
@@ -291,7 +311,7 @@ def test_sphere512_conv_sampled(sphere512, k):
     assert np.array_equal(nm, encode_oracle_map(src, idx))
 
 
-@pytest.mark.parametrize("name,k", [("sphere64", 5), ("rand33x20x70", 3)])
+@pytest.mark.parametrize("name,k", [("sphere64", 5), ("rand33x20x70", 3), ("sphere64", 13), ("rand33x20x70", 9)])
 def test_richardson_lucy_10_iterations(name, k):
     """APR Richardson-Lucy (10 iterations, restricted Gaussian PSF) against
     the FP64 oracle."""
