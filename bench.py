@@ -512,7 +512,7 @@ def main():
     acc = G.AprAccess.from_input(inp)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    log(f"access built: N_p={n_p} N_t={acc.n_tree} tiles={acc.n_tiles} ({build_ms:.1f} ms)")
+    log(f"access built: N_p={n_p} N_t={acc.n_tree} tiles={acc.n_tiles} work items={acc.n_work_items} ({build_ms:.1f} ms)")
 
     tree = torch.empty(acc.n_tree, dtype=torch.float32, device="cuda")
     y3 = torch.empty(n_p, dtype=torch.float32, device="cuda")
@@ -604,7 +604,7 @@ def main():
                                 f"{'device' if args.generator == 'device' else 'host'}; step = tree fill + "
                                 f"3^3 + 5^3 Gaussian (sigma 1) APR convolution, same stencil at every level"),
                    "n_particles": n_p, "n_tree": n_t, "pixels_per_particle": n_px / n_p,
-                   "tiles": acc.n_tiles, "generator": args.generator},
+                   "tiles": acc.n_tiles, "work_items": acc.n_work_items, "generator": args.generator},
         "pixel_equiv_GBps": n_px * 4 / (ms_per_step * 1e-3) / 1e9,
         "stages_ms": {"fill": fill_ms, "conv3": c3_ms, "conv5": c5_ms, "access_build_once": build_ms,
                       "apr_construction_once_s": gen_s, "tile_prepass": prepass_ms},

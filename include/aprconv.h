@@ -86,6 +86,7 @@ typedef struct {
   int64_t tree_per_level[APR_MAX_LEVELS];
   int64_t n_tiles;                       /* non-empty convolution tiles, all levels */
   int64_t device_bytes;                  /* device memory held by the handle */
+  int64_t n_work_items;                  /* convolution work items (runs of a tile's y windows) */
 } apr_access_info;
 
 typedef struct apr_handle apr_handle;
@@ -97,10 +98,11 @@ typedef struct apr_handle apr_handle;
  * tree (all interior nodes, Section 3.4: for every tree row the sorted union of
  * y/2 over the particles and tree nodes of its 2x2 child rows, finest level
  * first), the list of non-empty convolution tiles (the non-empty-row
- * pre-pass of Section 5.2, with each tile's first particle y; ordered for
- * launch as eight contiguous ranges of equal work, one per XCD, heaviest tiles
- * first, the work of a tile being the number of 64-cell chunks of its y sweep,
- * counted on the host) and the child list of every tree node (which
+ * pre-pass of Section 5.2, with each tile's first particle y), the
+ * convolution's work items (each tile's y sweep cut on the host into windows,
+ * runs of its particles' y spanning at most 64 cells; long sweeps cut into
+ * several items; ordered for launch as eight contiguous ranges of equal work,
+ * one per XCD, heaviest items first) and the child list of every tree node (which
  * apr_fill_tree gathers over).  Optional device validation per `desc->flags`
  * returns APR_EPARTITION / APR_EUNBALANCED.  Synchronizes `stream` before
  * returning.  The handle owns all its device memory; it is immutable after
@@ -125,8 +127,9 @@ apr_status apr_access_export_tree(const apr_handle* h, uint16_t* tree_y_idx, uin
  *                    particle y) of every tile of 8 x 8 (z, x) rows of one
  *                    level that holds a particle (Section 5.2's non-empty-row
  *                    pre-pass; tile (tz, tx) covers rows z in [8 tz, 8 tz + 8),
- *                    x in [8 tx, 8 tx + 8)), in launch order; b = int64 [9],
- *                    the start of each XCD's range of that list, then its end.
+ *                    x in [8 tx, 8 tx + 8)), finest level first, then tile z,
+ *                    tile x; b = int64 [9], the start of each XCD's range of
+ *                    the launch list of work items, then its end (n_work_items).
  * Either pointer may be NULL.  Unknown `which`: APR_EINVAL. */
 #define APR_EXPORT_APR 0
 #define APR_EXPORT_TREE 1

@@ -50,7 +50,7 @@ class AccessInfo(ctypes.Structure):
                 ("dims", (c_int32 * 3) * APR_MAX_LEVELS),
                 ("particles_per_level", c_int64 * APR_MAX_LEVELS),
                 ("tree_per_level", c_int64 * APR_MAX_LEVELS),
-                ("n_tiles", c_int64), ("device_bytes", c_int64)]
+                ("n_tiles", c_int64), ("device_bytes", c_int64), ("n_work_items", c_int64)]
 
 
 class ConvDesc(ctypes.Structure):

@@ -67,6 +67,7 @@ class AprAccess:
         self.l_min, self.l_max = int(info.l_min), int(info.l_max)
         self.tree_l_min, self.tree_l_max = int(info.tree_l_min), int(info.tree_l_max)
         self.n_tiles = int(info.n_tiles)
+        self.n_work_items = int(info.n_work_items)
         self.device_bytes = int(info.device_bytes)
         self.dims = tuple(int(v) for v in dims)
         self.level_dims = {l: tuple(info.dims[l]) for l in range(self.l_max + 1)}
@@ -104,8 +105,9 @@ class AprAccess:
         return y, e
 
     def export_tiles(self):
-        """Tile list [n_tiles, 4] (level, tile z, tile x, first y) in launch
-        order and the XCD range starts [9]."""
+        """Tile list [n_tiles, 4] (level, tile z, tile x, first y), finest
+        level first, and the XCD range starts [9] of the launch list of work
+        items."""
         t = np.zeros((self.n_tiles, 4), np.int32)
         off = np.zeros(9, np.int64)
         L.check(self._lib.apr_access_export(self.handle, L.APR_EXPORT_TILES, t.ctypes.data if t.size else None,

@@ -376,18 +376,28 @@ static void free_handle(apr_handle* h) {
 // (finest level first, then z, x) is cut into eight contiguous ranges of equal
 // cost, one per XCD (neighbouring tiles share halo rows in that XCD's L2), and
 // each range runs its heaviest tiles first, so that no long tile starts last.
+// Work items of the conv launch.  Each tile's y sweep is cut into windows
+// (runs of its output y spanning at most kWinY cells, gaps of at most kWinGap),
+// counted on the host from the LinearAccess.  A work item is a run of one
+// tile's windows: tiles whose sweep is long against the launch's ideal share
+// per workgroup slot are cut into several items (each starts with its own row
+// lookups), so that the longest item, not the longest tile, bounds the tail.
+// The items are split into eight contiguous ranges of equal cost, one per XCD,
+// each run heaviest first.
 static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream_t s) {
   const int64_t n = h->n_tiles;
-  for (int x = 0; x <= 8; ++x) h->xcd_off[x] = n * x / 8;
+  for (int x = 0; x <= 8; ++x) h->xcd_off[x] = 0;
+  h->n_items = 0;
   if (n == 0) return APR_OK;
   std::vector<uint64_t> t(size_t(n), 0);
   APR_HIP(hipMemcpyAsync(t.data(), h->tiles, size_t(n) * 8, hipMemcpyDeviceToHost, s));
   APR_HIP(hipStreamSynchronize(s));
   const Meta& m = h->meta;
-  std::vector<uint64_t> cost(size_t(n), 0);
   std::vector<uint32_t> wins;           // windows, tile by tile in list order
+  std::vector<uint32_t> wcost;          // cost of each window: its span + 16 cells
   std::vector<int64_t> woff(size_t(n) + 1, 0);
   std::vector<uint64_t> bits;
+  uint64_t total = 0;
   for (int64_t i = 0; i < n; ++i) {
     int l, tz, tx, y0;
     tile_unpack(t[size_t(i)], l, tz, tx, y0);
@@ -409,55 +419,69 @@ static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream
       }
       return -1;
     };
-    uint64_t c = 0;
     for (int y = next(0); y >= 0;) {
       const int w0 = y;
       int last = y, nx;
       while ((nx = next(last + 1)) >= 0 && nx - w0 < kWinY && nx - last - 1 <= kWinGap) last = nx;
       wins.push_back(uint32_t(w0) | (uint32_t(last) << 16));
-      c += uint64_t(last - w0 + 1) + 16;
+      wcost.push_back(uint32_t(last - w0 + 1) + 16);
+      total += wcost.back() + kItemCost;
       y = nx;
     }
-    cost[size_t(i)] = std::max<uint64_t>(c, 1);
     woff[size_t(i) + 1] = int64_t(wins.size());
   }
+  if (wins.size() >= (size_t(1) << 32)) APR_FAIL(APR_EUNSUPPORTED, "apr_access_build: too many sweep windows");
+  // items: runs of windows whose cost (item start included) stays within half
+  // the ideal share of one of the launch's resident workgroups
+  const uint64_t cap = std::max<uint64_t>(total / (2 * kConvSlots), 1);
+  std::vector<uint32_t> items;          // [n_items][4]: tile, first window, end window, 0
+  std::vector<uint64_t> cost;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t acc = kItemCost;
+    int64_t start = woff[size_t(i)];
+    for (int64_t w = woff[size_t(i)]; w < woff[size_t(i) + 1]; ++w) {
+      if (w > start && acc + wcost[size_t(w)] > cap) {
+        items.insert(items.end(), {uint32_t(i), uint32_t(start), uint32_t(w), 0u});
+        cost.push_back(acc);
+        acc = kItemCost;
+        start = w;
+      }
+      acc += wcost[size_t(w)];
+    }
+    items.insert(items.end(), {uint32_t(i), uint32_t(start), uint32_t(woff[size_t(i) + 1]), 0u});
+    cost.push_back(acc);
+  }
+  const int64_t ni = int64_t(cost.size());
   int64_t off[9];
-  for (int x = 0; x <= 8; ++x) off[x] = n * x / 8;
-  std::vector<int64_t> idx(static_cast<size_t>(n));
-  for (int64_t i = 0; i < n; ++i) idx[size_t(i)] = i;
-  if (n >= 16) {
-    uint64_t total = 0;
-    for (uint64_t c : cost) total += c;
+  for (int x = 0; x <= 8; ++x) off[x] = ni * x / 8;
+  std::vector<int64_t> idx(static_cast<size_t>(ni));
+  for (int64_t i = 0; i < ni; ++i) idx[size_t(i)] = i;
+  if (ni >= 16) {
+    uint64_t all = 0;
+    for (uint64_t c : cost) all += c;
     off[0] = 0;
-    off[8] = n;
+    off[8] = ni;
     uint64_t acc = 0;
     int x = 1;
-    for (int64_t i = 0; i < n && x < 8; ++i) {
+    for (int64_t i = 0; i < ni && x < 8; ++i) {
       acc += cost[size_t(i)];
-      while (x < 8 && acc * 8 >= total * uint64_t(x)) off[x++] = i + 1;
+      while (x < 8 && acc * 8 >= all * uint64_t(x)) off[x++] = i + 1;
     }
-    while (x < 8) off[x++] = n;
+    while (x < 8) off[x++] = ni;
     for (int r = 0; r < 8; ++r)
       std::stable_sort(idx.begin() + off[r], idx.begin() + off[r + 1],
                        [&](int64_t a, int64_t b) { return cost[size_t(a)] > cost[size_t(b)]; });
   }
-  std::vector<uint64_t> sorted(static_cast<size_t>(n));
-  std::vector<uint32_t> swins(wins.size());
-  std::vector<uint32_t> soff(size_t(n) + 1, 0);
-  size_t k = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    const size_t j = size_t(idx[size_t(i)]);
-    sorted[size_t(i)] = t[j];
-    for (int64_t q = woff[j]; q < woff[j + 1]; ++q) swins[k++] = wins[size_t(q)];
-    soff[size_t(i) + 1] = uint32_t(k);
-  }
+  std::vector<uint32_t> sorted(size_t(ni) * 4);
+  for (int64_t i = 0; i < ni; ++i)
+    std::copy_n(items.begin() + idx[size_t(i)] * 4, 4, sorted.begin() + i * 4);
   h->n_wins = int64_t(wins.size());
+  h->n_items = ni;
   apr_status st = dev_alloc(h, &h->wins, h->n_wins);
-  if (st == APR_OK) st = dev_alloc(h, &h->win_off, n + 1);
+  if (st == APR_OK) st = dev_alloc(h, &h->items, ni * 4);
   if (st != APR_OK) return st;
-  APR_HIP(hipMemcpyAsync(h->tiles, sorted.data(), size_t(n) * 8, hipMemcpyHostToDevice, s));
-  APR_HIP(hipMemcpyAsync(h->wins, swins.data(), swins.size() * 4, hipMemcpyHostToDevice, s));
-  APR_HIP(hipMemcpyAsync(h->win_off, soff.data(), soff.size() * 4, hipMemcpyHostToDevice, s));
+  APR_HIP(hipMemcpyAsync(h->wins, wins.data(), wins.size() * 4, hipMemcpyHostToDevice, s));
+  APR_HIP(hipMemcpyAsync(h->items, sorted.data(), sorted.size() * 4, hipMemcpyHostToDevice, s));
   APR_HIP(hipStreamSynchronize(s));
   for (int r = 0; r <= 8; ++r) h->xcd_off[r] = off[r];
   return APR_OK;
@@ -765,6 +789,7 @@ apr_status apr_access_get_info(const apr_handle* h, apr_access_info* o) {
   }
   o->n_tiles = h->n_tiles;
   o->device_bytes = h->device_bytes;
+  o->n_work_items = h->n_items;
   return APR_OK;
 }
 

@@ -44,6 +44,12 @@ constexpr int kTileX = 8;   // output rows per tile along x
 // stretch of more than kWinGap cells without outputs.
 constexpr int kWinY = 64;
 constexpr int kWinGap = 64;
+// Work-item cost model of the conv launch, in output cells: a window costs its
+// span + 16, starting an item (row lookups, first batches) kItemCost; items
+// are cut to at most half the ideal share of one of kConvSlots resident
+// workgroups (two 5^3 workgroups per CU on 256 CUs).
+constexpr uint64_t kItemCost = 32;
+constexpr uint64_t kConvSlots = 512;
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -161,12 +167,13 @@ struct apr_handle {
   uint32_t* pend = nullptr;   // particle row ends [n_rows]
   uint16_t* ty = nullptr;     // tree y [n_t]
   uint32_t* tend = nullptr;   // tree row ends [n_trows]
-  uint64_t* tiles = nullptr;  // conv tiles [n_tiles]: eight XCD ranges, heaviest first in each
+  uint64_t* tiles = nullptr;  // conv tiles [n_tiles]: level, tile z, tile x, first y
   int64_t n_tiles = 0;
   uint32_t* wins = nullptr;     // sweep windows of the tiles, in tile order: y0 | (y1 << 16)
-  uint32_t* win_off = nullptr;  // windows of tile t: [win_off[t], win_off[t + 1])
   int64_t n_wins = 0;
-  int64_t xcd_off[9] = {0};   // tiles of XCD x: [xcd_off[x], xcd_off[x + 1])
+  uint32_t* items = nullptr;    // conv work items [n_items][4]: tile, first window, end window, 0
+  int64_t n_items = 0;
+  int64_t xcd_off[9] = {0};   // items of XCD x: [xcd_off[x], xcd_off[x + 1]), heaviest first
   int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]
   uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t]
   // inverse of the gather maps for the coarse and tree taps: for source s

@@ -1,11 +1,12 @@
 // Single-channel APR convolution (Section 4.1), GPU design after Section 5.2,
 // re-shaped for wave64 / CDNA4.
 //
-// Work item: one tile of kTileZ x kTileX particle rows (z, x) at one level l,
-// from the non-empty tile list (the pre-pass of Section 5.2).  A workgroup
-// sweeps its tile along y through the tile's windows, made at access build:
-// runs of the tile's output y spanning at most kWinY cells (empty stretches
-// are skipped, the per-block y-range of Section 5.2).
+// Work item: a run of the y windows of one tile of kTileZ x kTileX particle
+// rows (z, x) at one level l, from the non-empty tile list (the pre-pass of
+// Section 5.2).  The windows are made at access build: runs of the tile's
+// output y spanning at most kWinY cells (empty stretches are skipped, the
+// per-block y-range of Section 5.2); a long sweep is cut into several items.
+// A workgroup sweeps its item's windows in y order.
 //
 // The level-l patch of a window covers the halo rows of the tile over
 // [y0 - r, y1 + r] and is reconstructed in LDS from three sorted sources:
@@ -56,9 +57,9 @@ struct ConvArgs {
   const uint32_t* tend;
   const uint64_t* tiles;
   const uint32_t* wins;      // sweep windows: y0 | (y1 << 16), outputs y0 <= y <= y1
-  const uint32_t* win_off;   // windows of tile t: [win_off[t], win_off[t + 1])
+  const uint32_t* items;     // work item i: tile, windows [first, end), at items[4 i]
   int64_t n_tiles;
-  int64_t xcd_off[9];     // tiles of XCD x: [xcd_off[x], xcd_off[x + 1])
+  int64_t xcd_off[9];     // work items of XCD x: [xcd_off[x], xcd_off[x + 1])
   const void* x;
   const void* tree;
   const float* w;
@@ -125,18 +126,19 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   const int gj = int(lane) - int(gbase);            // lane within the group
   const int grp = tid / G;
 
-  // XCD-aware tile order: block b runs on XCD b % 8, which takes its own
-  // contiguous range of the tile list (equal work per XCD, heaviest first).
+  // XCD-aware order: block b runs on XCD b % 8, which takes its own
+  // contiguous range of the work items (equal work per XCD, heaviest first).
   const int xcd = int(blockIdx.x % 8);
-  const int64_t t = a.xcd_off[xcd] + int64_t(blockIdx.x / 8);
-  if (t >= a.xcd_off[xcd + 1]) return;
+  const int64_t it = a.xcd_off[xcd] + int64_t(blockIdx.x / 8);
+  if (it >= a.xcd_off[xcd + 1]) return;
+  const uint32_t t = __builtin_amdgcn_readfirstlane(a.items[4 * it]);
   int l, tz, tx, ty0;
   tile_unpack(a.tiles[t], l, tz, tx, ty0);
   l = __builtin_amdgcn_readfirstlane(l);
   tz = __builtin_amdgcn_readfirstlane(tz);
   tx = __builtin_amdgcn_readfirstlane(tx);
-  const uint32_t w_beg = __builtin_amdgcn_readfirstlane(a.win_off[t]);
-  const uint32_t w_end = __builtin_amdgcn_readfirstlane(a.win_off[t + 1]);
+  const uint32_t w_beg = __builtin_amdgcn_readfirstlane(a.items[4 * it + 1]);
+  const uint32_t w_end = __builtin_amdgcn_readfirstlane(a.items[4 * it + 2]);
   const Meta& m = a.m;
   const int z0 = tz * TZ, x0 = tx * TXr;
   const int Dz = m.dz[l], Dx = m.dx[l], Dy = m.dy[l];
@@ -557,7 +559,7 @@ static ConvArgs base_args(const apr_handle* h) {
   a.tend = h->tend;
   a.tiles = h->tiles;
   a.wins = h->wins;
-  a.win_off = h->win_off;
+  a.items = h->items;
   a.n_tiles = h->n_tiles;
   for (int x = 0; x <= 8; ++x) a.xcd_off[x] = h->xcd_off[x];
   a.n_wlevels = 1;
