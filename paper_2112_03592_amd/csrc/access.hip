@@ -434,21 +434,22 @@ static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream
   // items: runs of windows whose cost (item start included) stays within half
   // the ideal share of one of the launch's resident workgroups
   const uint64_t cap = std::max<uint64_t>(total / (2 * kConvSlots), 1);
-  std::vector<uint32_t> items;          // [n_items][4]: tile, first window, end window, 0
+  std::vector<uint32_t> items;          // [n_items][4]: tile code (low, high word), first window, end window
   std::vector<uint64_t> cost;
   for (int64_t i = 0; i < n; ++i) {
     uint64_t acc = kItemCost;
     int64_t start = woff[size_t(i)];
     for (int64_t w = woff[size_t(i)]; w < woff[size_t(i) + 1]; ++w) {
       if (w > start && acc + wcost[size_t(w)] > cap) {
-        items.insert(items.end(), {uint32_t(i), uint32_t(start), uint32_t(w), 0u});
+        items.insert(items.end(), {uint32_t(t[size_t(i)]), uint32_t(t[size_t(i)] >> 32), uint32_t(start), uint32_t(w)});
         cost.push_back(acc);
         acc = kItemCost;
         start = w;
       }
       acc += wcost[size_t(w)];
     }
-    items.insert(items.end(), {uint32_t(i), uint32_t(start), uint32_t(woff[size_t(i) + 1]), 0u});
+    items.insert(items.end(), {uint32_t(t[size_t(i)]), uint32_t(t[size_t(i)] >> 32), uint32_t(start),
+                               uint32_t(woff[size_t(i) + 1])});
     cost.push_back(acc);
   }
   const int64_t ni = int64_t(cost.size());

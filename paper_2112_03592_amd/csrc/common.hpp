@@ -171,7 +171,7 @@ struct apr_handle {
   int64_t n_tiles = 0;
   uint32_t* wins = nullptr;     // sweep windows of the tiles, in tile order: y0 | (y1 << 16)
   int64_t n_wins = 0;
-  uint32_t* items = nullptr;    // conv work items [n_items][4]: tile, first window, end window, 0
+  uint32_t* items = nullptr;    // conv work items [n_items][4]: tile code (2 words), first window, end window
   int64_t n_items = 0;
   int64_t xcd_off[9] = {0};   // items of XCD x: [xcd_off[x], xcd_off[x + 1]), heaviest first
   int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]

@@ -57,7 +57,7 @@ struct ConvArgs {
   const uint32_t* tend;
   const uint64_t* tiles;
   const uint32_t* wins;      // sweep windows: y0 | (y1 << 16), outputs y0 <= y <= y1
-  const uint32_t* items;     // work item i: tile, windows [first, end), at items[4 i]
+  const uint32_t* items;     // work item i at items[4 i]: tile code (2 words), windows [first, end)
   int64_t n_tiles;
   int64_t xcd_off[9];     // work items of XCD x: [xcd_off[x], xcd_off[x + 1])
   const void* x;
@@ -84,11 +84,28 @@ __device__ inline uint32_t group_bits(uint64_t bal, uint32_t gbase) {
   return uint32_t(bal >> gbase) & ((1u << G) - 1u);
 }
 
+// LDS of one workgroup of the K^3 launch
+template <int K, bool INDEX>
+struct ConvLds {
+  static constexpr int R = K / 2, W = ConvShape<K>::kW;
+  static constexpr int NH = (kTileZ + 2 * R) * (kTileX + 2 * R);
+  static constexpr int PY = W + 2 * R, NC = kTileZ * kTileX;
+  using PT = typename std::conditional<INDEX, long long, float>::type;
+  PT patch[NH * PY];
+  uint32_t o_idx[NC * W];   // listed outputs of the patch: particle index
+  uint16_t o_pos[NC * W];   // (centre row << 6) | (y - y0)
+  uint32_t cnt[2];          // outputs listed, per window parity
+};
+
+// One work item: windows [w_beg, w_end) of tile (l, tz, tx), with the K^3
+// stencil read as the central K^3 of each level's KW^3 weights.  The LDS
+// buffers belong to a launch whose K is at least this K.
 // NF = 3: three stencils per level on the same patch (the three directions of
 // a gradient filter), output the magnitude sqrt(sum of squares).
-template <int K, typename TX, typename TY, bool INDEX, int NF = 1>
-__global__ __launch_bounds__(ConvShape<K>::kThreads)
-__attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
+template <int K, int KW, typename TX, typename TY, bool INDEX, int NF, typename PT>
+__device__ __forceinline__ void conv_item(const ConvArgs& a, int l, int tz, int tx, uint32_t w_beg, uint32_t w_end,
+                                          PT* __restrict__ patch, uint32_t* __restrict__ o_idx,
+                                          uint16_t* __restrict__ o_pos, uint32_t* __restrict__ s_cnt) {
   constexpr int NT = ConvShape<K>::kThreads;
   constexpr int G = ConvShape<K>::kG, NB = ConvShape<K>::kNB, GB = G * NB;
   constexpr int NG = NT / G;                         // lane groups
@@ -109,16 +126,13 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   constexpr int NC = TZ * TXr;                       // centre (output) rows
   constexpr int PY = W + 2 * R;
   constexpr int K3 = K * K * K;
+  constexpr int KW3 = KW * KW * KW, WO = (KW - K) / 2;   // weight set size, offset of the central K^3
   constexpr uint32_t kNone = 0xffffffffu;
   constexpr int kUnknown = -1;                       // y at the cursor not yet read
-  using PT = typename std::conditional<INDEX, long long, float>::type;
+  static_assert(std::is_same<PT, typename std::conditional<INDEX, long long, float>::type>::value, "patch type");
   static_assert(NC <= 64 && W <= 64 && TZ == TXr, "output positions pack into 12 bits");
   static_assert(64 % G == 0 && GB <= 32, "lane groups tile a wave; batch masks are 32-bit");
-
-  __shared__ PT patch[NH * PY];
-  __shared__ uint32_t o_idx[NC * W];   // listed outputs of the patch: particle index
-  __shared__ uint16_t o_pos[NC * W];   // (centre row << 6) | (y - y0)
-  __shared__ uint32_t s_cnt[2];            // outputs listed, per window parity
+  static_assert(KW >= K && (KW - K) % 2 == 0 && (KW == K || (!INDEX && NF == 1)), "central sub-stencil");
 
   const int tid = threadIdx.x;
   const uint32_t lane = lane_id();
@@ -126,19 +140,6 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   const int gj = int(lane) - int(gbase);            // lane within the group
   const int grp = tid / G;
 
-  // XCD-aware order: block b runs on XCD b % 8, which takes its own
-  // contiguous range of the work items (equal work per XCD, heaviest first).
-  const int xcd = int(blockIdx.x % 8);
-  const int64_t it = a.xcd_off[xcd] + int64_t(blockIdx.x / 8);
-  if (it >= a.xcd_off[xcd + 1]) return;
-  const uint32_t t = __builtin_amdgcn_readfirstlane(a.items[4 * it]);
-  int l, tz, tx, ty0;
-  tile_unpack(a.tiles[t], l, tz, tx, ty0);
-  l = __builtin_amdgcn_readfirstlane(l);
-  tz = __builtin_amdgcn_readfirstlane(tz);
-  tx = __builtin_amdgcn_readfirstlane(tx);
-  const uint32_t w_beg = __builtin_amdgcn_readfirstlane(a.items[4 * it + 1]);
-  const uint32_t w_end = __builtin_amdgcn_readfirstlane(a.items[4 * it + 2]);
   const Meta& m = a.m;
   const int z0 = tz * TZ, x0 = tx * TXr;
   const int Dz = m.dz[l], Dx = m.dx[l], Dy = m.dy[l];
@@ -148,7 +149,9 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   const uint16_t* __restrict__ py = a.py;
   const uint16_t* __restrict__ ty = a.ty;
   using cfloat = const __attribute__((address_space(4))) float;
-  cfloat* wl = (cfloat*)(uintptr_t)(INDEX ? a.w : a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * K3 * NF);
+  cfloat* wl = (cfloat*)(uintptr_t)(INDEX ? a.w
+                                           : a.w + (a.n_wlevels == 1 ? 0 : (l - m.l_min)) * KW3 * NF +
+                                                 (WO * KW + WO) * KW + WO);
   const PT pad = INDEX ? PT(-1) : PT(0);
 
   // ---- setup: each group owns source rows s = grp + r * NG for the whole
@@ -469,16 +472,16 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
         float g0 = 0.f, g1 = 0.f, g2 = 0.f;
 #pragma unroll
         for (int dz = 0; dz < K; ++dz) {
-          cfloat* wz = wl + dz * K * K;
+          cfloat* wz = wl + dz * KW * KW;
 #pragma unroll
           for (int dx = 0; dx < K; ++dx) {
             const float* row = pb + (dz * HX + dx) * PY;
 #pragma unroll
             for (int dy = 0; dy < K; ++dy) {
               const float v = row[dy];
-              g0 = fmaf(wz[dx * K + dy], v, g0);
-              g1 = fmaf(wz[K3 + dx * K + dy], v, g1);
-              g2 = fmaf(wz[2 * K3 + dx * K + dy], v, g2);
+              g0 = fmaf(wz[dx * KW + dy], v, g0);
+              g1 = fmaf(wz[KW3 + dx * KW + dy], v, g1);
+              g2 = fmaf(wz[2 * KW3 + dx * KW + dy], v, g2);
             }
           }
         }
@@ -487,12 +490,12 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
         float acc = 0.f;
 #pragma unroll(K == 3 ? K : 1)
         for (int dz = 0; dz < K; ++dz) {
-          cfloat* wz = wl + dz * K * K;
+          cfloat* wz = wl + dz * KW * KW;
 #pragma unroll(K <= 5 ? K : 1)
           for (int dx = 0; dx < K; ++dx) {
             const float* row = pb + (dz * HX + dx) * PY;
 #pragma unroll
-            for (int dy = 0; dy < K; ++dy) acc = fmaf(wz[dx * K + dy], row[dy], acc);
+            for (int dy = 0; dy < K; ++dy) acc = fmaf(wz[dx * KW + dy], row[dy], acc);
           }
         }
         TY* yo = static_cast<TY*>(a.y);
@@ -514,6 +517,55 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
     y1 = ny1;
     par ^= 1;
   }
+}
+
+// true if the KW^3 weight set at w has only zeros outside its central 3^3
+// (restricted stencils at the coarser levels, Eq. restrict_stenc); w uniform
+template <int KW>
+__device__ inline bool outer_shell_zero(const float* w) {
+  using cfloat = const __attribute__((address_space(4))) float;
+  cfloat* c = (cfloat*)(uintptr_t)w;
+  uint32_t any = 0;
+#pragma unroll
+  for (int q = 0; q < KW * KW * KW; ++q) {
+    const int z = q / (KW * KW), x = (q / KW) % KW, y = q % KW, o = KW / 2;
+    if (abs(z - o) > 1 || abs(x - o) > 1 || abs(y - o) > 1) any |= __builtin_bit_cast(uint32_t, c[q]) << 1;
+  }
+  return any == 0;   // +0 and -0 both count as zero
+}
+
+// XCD-aware order: block b runs on XCD b % 8, which takes its own contiguous
+// range of the work items (equal work per XCD, heaviest first).  A 5^3
+// single-channel launch runs a tile with the 3^3 body when its level's weights
+// vanish outside the central 3^3: every nonzero tap is then taken in the same
+// order, so the outputs are the same (for finite values).
+template <int K, typename TX, typename TY, bool INDEX, int NF = 1>
+__global__ __launch_bounds__(ConvShape<K>::kThreads)
+__attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) void conv1_kernel(ConvArgs a) {
+  __shared__ ConvLds<K, INDEX> lds;
+  const int xcd = int(blockIdx.x % 8);
+  const int64_t it = a.xcd_off[xcd] + int64_t(blockIdx.x / 8);
+  if (it >= a.xcd_off[xcd + 1]) return;
+  const uint4 item = reinterpret_cast<const uint4*>(a.items)[it];
+  int l, tz, tx, ty0;
+  tile_unpack(uint64_t(__builtin_amdgcn_readfirstlane(item.x)) |
+                  (uint64_t(__builtin_amdgcn_readfirstlane(item.y)) << 32),
+              l, tz, tx, ty0);
+  l = __builtin_amdgcn_readfirstlane(l);
+  tz = __builtin_amdgcn_readfirstlane(tz);
+  tx = __builtin_amdgcn_readfirstlane(tx);
+  const uint32_t w_beg = __builtin_amdgcn_readfirstlane(item.z);
+  const uint32_t w_end = __builtin_amdgcn_readfirstlane(item.w);
+  if constexpr (K == 5 && !INDEX && NF == 1) {
+    static_assert(ConvShape<3>::kThreads == ConvShape<5>::kThreads && sizeof(ConvLds<3, false>) <= sizeof(lds),
+                  "the 3^3 body runs in the 5^3 launch shape");
+    const float* wl = a.w + (a.n_wlevels == 1 ? 0 : (l - a.m.l_min)) * 125;
+    if (outer_shell_zero<5>(wl)) {
+      conv_item<3, 5, TX, TY, false, 1>(a, l, tz, tx, w_beg, w_end, lds.patch, lds.o_idx, lds.o_pos, lds.cnt);
+      return;
+    }
+  }
+  conv_item<K, K, TX, TY, INDEX, NF>(a, l, tz, tx, w_beg, w_end, lds.patch, lds.o_idx, lds.o_pos, lds.cnt);
 }
 
 

@@ -156,6 +156,35 @@ def test_conv_large_stencils(name, k, mode):
     assert_close_scaled(y, ref, scale, 1e-5, f"{name} k={k} {mode}")
 
 
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_conv5_central_3cubed_levels(name):
+    """Levels whose 5^3 weights vanish outside the central 3^3 (restricted
+    stencils at coarse levels, Eq. restrict_stenc) run the 3^3 body in the 5^3
+    launch: bit-identical to the 3^3 convolution with those weights, and, with
+    the finest level keeping a full 5^3 stencil, within the FP32 bar of the
+    oracle."""
+    say("conv5 central 3^3", name)
+    inp, la, tr = case(name)
+    nl = la.l_max - la.l_min + 1
+    rng = np.random.default_rng(53)
+    w3 = rng.normal(size=(nl, 3, 3, 3)).astype(np.float32)
+    w5 = np.zeros((nl, 5, 5, 5), np.float32)
+    w5[:, 1:4, 1:4, 1:4] = w3
+    mixed = w5.copy()
+    mixed[-1] = rng.normal(size=(5, 5, 5)).astype(np.float32)   # the finest level: full 5^3
+    x64 = inp.values.astype(np.float64)
+    with G.AprAccess.from_input(inp) as acc:
+        x = torch.from_numpy(inp.values).cuda()
+        t = G.fill_tree(acc, x)
+        y3 = G.conv(acc, x, t, torch.from_numpy(w3).cuda(), 3).cpu().numpy()
+        y5 = G.conv(acc, x, t, torch.from_numpy(w5).cuda(), 5).cpu().numpy()
+        ym = G.conv(acc, x, t, torch.from_numpy(mixed).cuda(), 5).cpu().numpy()
+    assert np.array_equal(y3, y5)
+    ref = C.apr_conv(la, x64, mixed.astype(np.float64), tree=tr)
+    scale = C.apr_conv(la, np.abs(x64), np.abs(mixed.astype(np.float64)), tree=tr)
+    assert_close_scaled(ym, ref, scale, 1e-5, f"{name} mixed 3^3 / 5^3 levels")
+
+
 @pytest.mark.parametrize("name", ["rand16_l1", "rand33x20x70", "sphere64"])
 def test_conv_shared_stencil_and_signed_values(name):
     inp, la, tr = case(name)
