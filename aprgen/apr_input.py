@@ -754,6 +754,17 @@ def _deconv_job(args):
     return a
 
 
+def input_digest(inp) -> str:
+    """SHA-256 of an APR input's LinearAccess and values (pairs stored results
+    with the input they were computed from)."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (np.asarray(inp.y_idx, np.uint16), np.asarray(inp.xz_end, np.uint64),
+              np.asarray(inp.values, np.float32)):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
 def deconv_set(edges: Sequence[int], seed0: int, workers: int = 1, progress=None):
     """APRs of the deconvolution workload with seeds seed0, seed0 + 1, ...;
     generated in ``workers`` processes; ``progress(edge, n_particles)`` is

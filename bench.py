@@ -338,6 +338,11 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
     from paper_2112_03592_amd import apr as G
     from paper_2112_03592_amd import surrogate as N
     edges = SURROGATE_EVAL[which]
+    # the FP64 oracle's RL10 of the 256^3 batch APR, stored by
+    # tests/golden/make_rl10_deconv256.py (a file, not oracle code)
+    from aprgen.apr_input import input_digest
+    gold_path = os.path.join(ROOT, "tests", "golden", "rl10_deconv256.npz")
+    gold = np.load(gold_path) if os.path.exists(gold_path) else None
     sur = N.load_surrogate(weights)
     sur8 = N.load_surrogate(weights, act_dtype=torch.float8_e4m3fn)
     ws = G.Workspace(16)
@@ -367,6 +372,13 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
         rec["error"].append(N.rel_error(res.values, t, ws))
         rec["monitor"].append(res.monitor)
         rec["fallback"].append(bool(res.fallback))
+        if gold is not None and inp.dims[0] == int(gold["edge"]) and str(gold["digest"]) == input_digest(inp):
+            g = torch.from_numpy(gold["rl10"]).cuda()
+            rec["vs_fp64_oracle"] = {"edge": int(gold["edge"]), "n_particles": inp.n_particles,
+                                     "surrogate": N.rel_error(res.values, g, ws),
+                                     "plain_rl10": N.rel_error(t, g, ws),
+                                     "source": "tests/golden/rl10_deconv256.npz (FP64 oracle RL10, stored in FP32)"}
+            del g
         # the same network with FP8 (E4M3) hidden activations
         res8 = sur8(acc, u)
         torch.cuda.synchronize()
@@ -385,6 +397,7 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
         sur8.rl.forget(acc)
         acc.close()
         del t, res, u
+    rec["error_reference"] = "device RL10 (FP32); vs_fp64_oracle: the FP64 oracle at the 256^3 APR"
     rec["speedup"] = float(np.sum(rec["plain_ms"]) / np.sum(rec["surrogate_ms"]))
     rec["fp8"]["speedup"] = float(np.sum(rec["plain_ms"]) / np.sum(rec["fp8"]["surrogate_ms"]))
     rec["fp8"]["max_error"] = float(np.max(rec["fp8"]["error"]))

@@ -295,6 +295,37 @@ def test_trained_surrogate_against_fp64_oracle_rl10(edge, seed):
     assert np.array_equal(got, plain if res.fallback else est)
 
 
+GOLDEN_RL10 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rl10_deconv256.npz")
+
+
+def test_bench_size_surrogate_against_stored_oracle_rl10():
+    """The first APR of the benchmark batch (256^3, seed 7000, 0.5M
+    particles) against the FP64 oracle's RL10, stored by
+    tests/golden/make_rl10_deconv256.py (a digest of the input guards the
+    pairing): the device RL10 within 1e-4, the surrogate's returned values
+    within 2e-2."""
+    from aprgen.apr_input import input_digest
+    gold = np.load(GOLDEN_RL10)
+    inp = deconv_set([int(gold["edge"])], int(gold["seed"]))[0]
+    assert str(gold["digest"]) == input_digest(inp), "stored oracle RL10 belongs to another input"
+    t = gold["rl10"].astype(np.float64)
+    u = np.maximum(inp.values, 0).astype(np.float32)
+    sur = N.load_surrogate(TRAINED)
+    with G.AprAccess.from_input(inp, gather=(3,)) as acc:
+        ud = dev(u)
+        plain = G.richardson_lucy(acc, ud, deconv_psf(), 10).cpu().numpy().astype(np.float64)
+        res = sur(acc, ud)
+        got = res.values.cpu().numpy().astype(np.float64)
+
+    def err(a):
+        return float(np.linalg.norm(a - t) / np.linalg.norm(t))
+
+    say(f"  256^3: plain FP32 {err(plain):.2e}, surrogate {err(got):.4f} (monitor {res.monitor:.4f}, "
+        f"fallback {res.fallback})")
+    assert err(plain) < 1e-4
+    assert err(got) <= 2e-2
+
+
 def test_short_training_reduces_the_loss():
     rl = N.RichardsonLucy(deconv_psf())
     cases = []
