@@ -232,7 +232,7 @@ apr_status apr_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, 
  * W_l[co][ci][o] V_l[ci](c_p + o)) runs on the gather map and needs the handle
  * built with APR_BUILD_GATHER3 / APR_BUILD_GATHER5 for d->k.  Supported
  * (c_in, c_out): k = 3: (1,1) (1,16) (16,16) (16,1) (2,3); k = 5: (1,1) (2,3).
- * k = 3, 16 -> 16 runs on matrix cores: with BF16 x and tree (8-byte aligned)
+ * k = 3, 16 -> 16 runs on matrix cores: with BF16 x and tree (16-byte aligned)
  * the weights are rounded to BF16 (FP32 accumulation); with FP32 x and tree
  * (16-byte aligned) FP32 throughout.  FP8 storage (network activations):
  * k = 3 only; x FP8 with (16,16) (4-byte aligned x and tree; BF16 weights on

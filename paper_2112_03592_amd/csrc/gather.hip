@@ -295,6 +295,92 @@ __device__ inline mfma_s4 fp8x4_to_bf16(uint32_t c) {
                  short(__float_as_uint(f[2]) >> 16), short(__float_as_uint(f[3]) >> 16)};
 }
 
+typedef __bf16 mfma_b8 __attribute__((ext_vector_type(8)));
+
+// 16 -> 16 channels, 3^3, BF16 rows on v_mfma_f32_16x16x32_bf16 (gfx950).  The reduction axis of instruction m (m = 0..13)
+// is two taps x 16 input channels: lane l (r16 = l % 16, kg = l / 16) holds
+// A[particle r16][k = 8 kg + i] = row(tap 2m + kg / 2)[8 (kg % 2) + i], one
+// 16-byte load, and B[k][n = r16] = W[r16][8 (kg % 2) + i][2m
+// + kg / 2] staged in LDS; tap 27 is zero.  D: lane l holds outputs 4 kg + i
+// of channel r16.  Persistent waves over an XCD-contiguous tile range.  Half
+// the row loads and MFMA instructions of the 16x16x16 form below.
+template <typename TX, typename TY>
+__global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma32_kernel(
+    const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end,
+    const TX* __restrict__ x, const TX* __restrict__ tree, const float* __restrict__ w_level,
+    const float* __restrict__ bias, int relu, const TY* __restrict__ residual, TY* __restrict__ y) {
+  constexpr int K3 = 27, NM = 14;
+  static_assert(std::is_same<TX, __hip_bfloat16>::value, "BF16 rows");
+  // B operands of the level, [instruction][lane], staged once per block
+  __shared__ uint4 sb[NM][64];
+  for (int j = threadIdx.x; j < NM * 64; j += 64 * kMfmaWaves) {
+    const int m = j / 64, ln = j % 64, n = ln & 15, q = 2 * m + (ln >> 5), c = 8 * ((ln >> 4) & 1);
+    uint32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t lo = q < K3 ? uint16_t(bf16_bits(w_level[(n * 16 + c + 2 * i) * K3 + q])) : 0u;
+      const uint32_t hi = q < K3 ? uint16_t(bf16_bits(w_level[(n * 16 + c + 2 * i + 1) * K3 + q])) : 0u;
+      v[i] = lo | (hi << 16);
+    }
+    sb[m][ln] = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+  __syncthreads();
+  // XCD blockIdx % 8 takes the contiguous tile range [tb, te); its waves
+  // stride through it
+  const uint32_t n_tiles = (p_end - p_begin + 15) / 16;
+  const uint32_t per = (n_tiles + 7) / 8;
+  const uint32_t tb = (blockIdx.x % 8) * per;
+  const uint32_t te = min(n_tiles, tb + per);
+  const uint32_t waves_per_xcd = (gridDim.x / 8) * kMfmaWaves;
+  uint32_t tile = tb + (blockIdx.x / 8) * kMfmaWaves + threadIdx.x / 64;
+  if (tile >= te) return;
+  const int lane = int(threadIdx.x & 63);
+  const int r16 = lane & 15, kg = lane >> 4, half = kg & 1, qo = kg >> 1;
+  const float bco = bias ? bias[r16] : 0.f;
+  // map entries of this lane's taps for particle r16 of a tile (kPad past the end)
+  auto load_map = [&](uint32_t tl, uint32_t (&g)[NM]) {
+    const uint32_t p = p_begin + tl * 16 + uint32_t(r16);
+    const bool valid = tl < te && p < p_end;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int q = 2 * m + qo;
+      g[m] = (valid && q < K3) ? gmap[size_t(q) * size_t(n_p) + p] : kPad;
+    }
+  };
+  uint32_t g[NM];
+  load_map(tile, g);
+  for (; tile < te; tile += waves_per_xcd) {
+    uint4 a[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      a[m] = make_uint4(0u, 0u, 0u, 0u);
+      if (g[m] != kPad) {
+        const TX* row = ((g[m] >> 30) == 3 ? tree : x) + size_t(g[m] & kIdxMask) * 16;
+        a[m] = *reinterpret_cast<const uint4*>(row + 8 * half);
+      }
+    }
+    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(mfma_b8, a[m]),
+                                                    __builtin_bit_cast(mfma_b8, sb[m][lane]), acc, 0, 0, 0);
+    const uint32_t t0 = p_begin + tile * 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t pm = t0 + 4 * kg + i;
+      if (pm >= p_end) continue;
+      float o = acc[i] + bco;
+      if (residual) o += to_f32<TY>(residual[size_t(pm) * 16 + r16]);
+      if (relu) o = fmaxf(o, 0.f);
+      y[size_t(pm) * 16 + r16] = from_f32<TY>(o);
+    }
+    load_map(tile + waves_per_xcd, g);
+  }
+}
+
+// 16 -> 16 channels, 3^3, on v_mfma_f32_16x16x16_bf16 (FP8 rows, widened
+// exactly): lane l (r16 = l % 16, kg = l / 16) holds A[particle r16][input
+// channel 4 kg + i] of a tap and B[4 kg + i][output channel r16].
 template <typename TX, typename TY>
 __global__ __launch_bounds__(64 * kMfmaWaves) void mc16_mfma_kernel(
     const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end,
@@ -373,10 +459,12 @@ static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const 
       const uint32_t tiles = (np_l + 15) / 16;
       // enough waves to fill every CU (3 per SIMD), no more than one per tile
       const uint32_t blocks_per_xcd = std::min<uint32_t>(kMfmaBlocksPerXcd, (tiles / 8 + kMfmaWaves) / kMfmaWaves);
-      hipLaunchKernelGGL((mc16_mfma_kernel<TX, TY>), dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)),
-                         dim3(64 * kMfmaWaves), 0, s, reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p,
-                         begin, begin + np_l, static_cast<const TX*>(x), static_cast<const TX*>(tree), wl, d->bias,
-                         d->relu,
+      void (*kern)(const uint32_t*, int64_t, uint32_t, uint32_t, const TX*, const TX*, const float*, const float*,
+                   int, const TY*, TY*) = mc16_mfma_kernel<TX, TY>;
+      if constexpr (std::is_same<TX, __hip_bfloat16>::value) kern = mc16_mfma32_kernel<TX, TY>;
+      hipLaunchKernelGGL(kern, dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)), dim3(64 * kMfmaWaves), 0, s,
+                         reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p, begin, begin + np_l,
+                         static_cast<const TX*>(x), static_cast<const TX*>(tree), wl, d->bias, d->relu,
                          static_cast<const TY*>(d->residual), static_cast<TY*>(y));
     }
     begin += np_l;
@@ -560,7 +648,7 @@ apr_status mc_conv(const apr_handle* h, const apr_conv_desc* d, const void* x, c
   const int cin = d->c_in, cout = d->c_out;
   if (d->x_dtype == APR_FP8 || d->y_dtype == APR_FP8) return mc_conv_fp8(h, d, x, tree, w, y, s);
   if (d->k == 3 && cin == 16 && cout == 16 && d->x_dtype == APR_BF16 &&
-      ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 7) == 0) {
+      ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(tree)) & 15) == 0) {
     if (d->y_dtype == APR_BF16)
       launch_mc16_mfma<__hip_bfloat16, __hip_bfloat16>(h, d, x, tree, w, y, s);
     else
