@@ -31,8 +31,12 @@
 namespace apr {
 
 constexpr int kBig = 1 << 28;    // key of a missing element
-// Launch shape per stencil size.  Source rows are served by groups of kG
-// lanes; each group moves kG * kNB elements of its row per memory round.  A
+// Launch shape per stencil size: 3^3 in 1024-thread workgroups capped at 64
+// registers (two per CU, eight waves per SIMD), 5^3 in 768-thread workgroups
+// capped at 80 (two per CU, six waves per SIMD; at 64 it spills), larger
+// stencils in 1024-thread workgroups at four waves per SIMD.  Source rows are
+// served by groups of kG lanes; each group moves kG * kNB elements of its row
+// per memory round.  A
 // patch holds output y spans of at most kW cells.  Within radius r of a
 // level-l particle, 26-neighbour 2:1 balance admits particles of level l - j
 // only at distances of at least 2^j - 1 cells, so stencils up to 5^3 read APR
@@ -41,10 +45,10 @@ template <int K>
 struct ConvShape {
   static_assert(K % 2 == 1 && K >= 3 && K <= 13, "odd stencil sides 3..13");
   static constexpr bool kLarge = K > 5;
-  static constexpr int kThreads = kLarge ? 1024 : 768;
+  static constexpr int kThreads = kLarge || K == 3 ? 1024 : 768;
   static constexpr int kG = 8;
   static constexpr int kNB = kLarge ? 1 : 2;
-  static constexpr int kWavesPerSimd = kLarge ? 4 : 6;
+  static constexpr int kWavesPerSimd = kLarge ? 4 : K == 3 ? 8 : 6;
   static constexpr int kW = kLarge ? 16 : kWinY;
   static constexpr int kDepth = kLarge ? 2 : 1;   // coarsest APR source level: l - kDepth
   // patch row stride (floats): the y span plus the halo, padded up to 8 mod 32
@@ -106,11 +110,10 @@ struct ConvLds {
 // buffers belong to a launch whose K is at least this K.
 // NF = 3: three stencils per level on the same patch (the three directions of
 // a gradient filter), output the magnitude sqrt(sum of squares).
-template <int K, int KW, typename TX, typename TY, bool INDEX, int NF, typename PT>
+template <int K, int KW, typename TX, typename TY, bool INDEX, int NF, int NT, typename PT>
 __device__ __forceinline__ void conv_item(const ConvArgs& a, int l, int tz, int tx, uint32_t w_beg, uint32_t w_end,
                                           PT* __restrict__ patch, uint32_t* __restrict__ o_idx,
                                           uint16_t* __restrict__ o_pos, uint32_t* __restrict__ s_cnt) {
-  constexpr int NT = ConvShape<K>::kThreads;
   constexpr int G = ConvShape<K>::kG, NB = ConvShape<K>::kNB, GB = G * NB;
   constexpr int NG = NT / G;                         // lane groups
   constexpr int R = K / 2;
@@ -561,15 +564,16 @@ __attribute__((amdgpu_waves_per_eu(INDEX ? 3 : ConvShape<K>::kWavesPerSimd))) vo
   const uint32_t w_beg = __builtin_amdgcn_readfirstlane(item.z);
   const uint32_t w_end = __builtin_amdgcn_readfirstlane(item.w);
   if constexpr (K == 5 && !INDEX && NF == 1) {
-    static_assert(ConvShape<3>::kThreads == ConvShape<5>::kThreads && sizeof(ConvLds<3, false>) <= sizeof(lds),
-                  "the 3^3 body runs in the 5^3 launch shape");
+    static_assert(sizeof(ConvLds<3, false>) <= sizeof(lds), "the 3^3 body runs in the 5^3 launch's LDS");
     const float* wl = a.w + (a.n_wlevels == 1 ? 0 : (l - a.m.l_min)) * 125;
     if (outer_shell_zero<5>(wl)) {
-      conv_item<3, 5, TX, TY, false, 1>(a, l, tz, tx, w_beg, w_end, lds.patch, lds.o_idx, lds.o_pos, lds.cnt);
+      conv_item<3, 5, TX, TY, false, 1, ConvShape<5>::kThreads>(a, l, tz, tx, w_beg, w_end, lds.patch, lds.o_idx,
+                                                                lds.o_pos, lds.cnt);
       return;
     }
   }
-  conv_item<K, K, TX, TY, INDEX, NF>(a, l, tz, tx, w_beg, w_end, lds.patch, lds.o_idx, lds.o_pos, lds.cnt);
+  conv_item<K, K, TX, TY, INDEX, NF, ConvShape<K>::kThreads>(a, l, tz, tx, w_beg, w_end, lds.patch, lds.o_idx, lds.o_pos,
+                                                             lds.cnt);
 }
 
 
