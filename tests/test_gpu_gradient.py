@@ -35,6 +35,13 @@ def _scale(la, tr, x64, w3, sample=None):
     return np.sqrt(sq)
 
 
+def _oracle_sobel_levels(la):
+    """The reference side's per-level Sobel stencils [nl, 3, 3, 3, 3], built by
+    the oracle (Eq. adapt_grad), independently of the library's."""
+    return np.moveaxis(np.stack([S.level_stencils(s_, S.ADAPTIVE, la.l_min, la.l_max) for s_ in sobel_stencils()]),
+                       0, 1)
+
+
 @pytest.mark.parametrize("name", ["rand16_l1", "rand33x20x70", "rand_long_y", "sphere32", "sphere64",
                                   "dense13x11x70", "single_cell"])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
@@ -47,7 +54,7 @@ def test_gradient_magnitude(name, storage):
     if storage == "bf16":
         x = x.to(torch.bfloat16)
     x64 = x.float().cpu().numpy().astype(np.float64)
-    w64 = w3.astype(np.float64)
+    w64 = _oracle_sobel_levels(la)
     ref = C.gradient_magnitude(la, x64, w64, tree=tr)
     scale = _scale(la, tr, x64, w64)
     with G.AprAccess.from_input(inp) as acc:
@@ -65,8 +72,9 @@ def test_gradient_magnitude_sphere512_sampled():
     w3 = G.stencil_levels(sobel_stencils(), "adaptive", 3, la.l_min, la.l_max)
     smp = np.sort(np.random.default_rng(11).choice(la.n, 4096, replace=False))
     x64 = inp.values.astype(np.float64)
-    ref = C.gradient_magnitude(la, x64, w3.astype(np.float64), tree=tr, sample=smp)
-    scale = _scale(la, tr, x64, w3.astype(np.float64), sample=smp)
+    w64 = _oracle_sobel_levels(la)
+    ref = C.gradient_magnitude(la, x64, w64, tree=tr, sample=smp)
+    scale = _scale(la, tr, x64, w64, sample=smp)
     with G.AprAccess.from_input(inp) as acc:
         x = torch.from_numpy(inp.values).cuda()
         t = G.fill_tree(acc, x)

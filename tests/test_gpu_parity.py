@@ -109,14 +109,17 @@ def test_fill_tree_fp32(name):
 
 
 def _weights(k, mode, la, seed):
+    """(library FP32 stencils for the GPU, the oracle's FP64 stencils for the
+    reference): per-level stencils are built on each side independently."""
     rng = np.random.default_rng(seed)
     if mode == "explicit":
         w = rng.normal(size=(la.l_max - la.l_min + 1, k, k, k)).astype(np.float32)
-        return w
+        return w, w.astype(np.float64)
     if mode == "asym":
         w = rng.normal(size=(k, k, k))
-        return G.stencil_levels(w, "same", k, la.l_min, la.l_max)
-    return G.stencil_levels(S.gaussian_stencil(k, 1.0), mode, k, la.l_min, la.l_max)
+        return G.stencil_levels(w, "same", k, la.l_min, la.l_max), S.level_stencils(w, S.SAME, la.l_min, la.l_max)
+    g = S.gaussian_stencil(k, 1.0)
+    return G.stencil_levels(g, mode, k, la.l_min, la.l_max), S.level_stencils(g, mode, la.l_min, la.l_max)
 
 
 @pytest.mark.parametrize("name", list(SMALL_CASES))
@@ -125,10 +128,10 @@ def _weights(k, mode, la, seed):
 def test_conv_fp32(name, k, mode):
     say("conv fp32", name, k, mode)
     inp, la, tr = case(name)
-    w32 = _weights(k, mode, la, seed=k)
+    w32, w64 = _weights(k, mode, la, seed=k)
     x64 = inp.values.astype(np.float64)
-    ref = C.apr_conv(la, x64, w32.astype(np.float64), tree=tr)
-    scale = C.apr_conv(la, np.abs(x64), np.abs(w32.astype(np.float64)), tree=tr)
+    ref = C.apr_conv(la, x64, w64, tree=tr)
+    scale = C.apr_conv(la, np.abs(x64), np.abs(w64), tree=tr)
     with G.AprAccess.from_input(inp) as acc:
         x = torch.from_numpy(inp.values).cuda()
         t = G.fill_tree(acc, x)
@@ -145,10 +148,10 @@ def test_conv_large_stencils(name, k, mode):
     output cells along y."""
     say("conv large", name, k, mode)
     inp, la, tr = case(name)
-    w32 = _weights(k, mode, la, seed=k)
+    w32, w64 = _weights(k, mode, la, seed=k)
     x64 = inp.values.astype(np.float64)
-    ref = C.apr_conv(la, x64, w32.astype(np.float64), tree=tr)
-    scale = C.apr_conv(la, np.abs(x64), np.abs(w32.astype(np.float64)), tree=tr)
+    ref = C.apr_conv(la, x64, w64, tree=tr)
+    scale = C.apr_conv(la, np.abs(x64), np.abs(w64), tree=tr)
     with G.AprAccess.from_input(inp) as acc:
         x = torch.from_numpy(inp.values).cuda()
         t = G.fill_tree(acc, x)
@@ -218,7 +221,7 @@ def test_conv_is_deterministic():
     inp, la, tr = case("sphere64")
     with G.AprAccess.from_input(inp) as acc:
         x = torch.from_numpy(inp.values).cuda()
-        w = torch.from_numpy(_weights(5, "restrict", la, 0)).cuda()
+        w = torch.from_numpy(_weights(5, "restrict", la, 0)[0]).cuda()
         t1 = G.fill_tree(acc, x)
         y1 = G.conv(acc, x, t1, w, 5)
         t2 = G.fill_tree(acc, x)
@@ -232,12 +235,12 @@ def test_conv_bf16_storage(name, k):
     """BF16 particle and tree storage, FP32 accumulation: within 1e-2 * M_p of
     the oracle on the BF16-rounded particle values."""
     inp, la, tr = case(name)
-    w32 = _weights(k, "restrict", la, 0)
+    w32, w64 = _weights(k, "restrict", la, 0)
     with G.AprAccess.from_input(inp) as acc:
         xb = torch.from_numpy(inp.values).cuda().to(torch.bfloat16)
         x64 = xb.float().cpu().numpy().astype(np.float64)
-        ref = C.apr_conv(la, x64, w32.astype(np.float64), tree=tr)
-        scale = C.apr_conv(la, np.abs(x64), np.abs(w32.astype(np.float64)), tree=tr)
+        ref = C.apr_conv(la, x64, w64, tree=tr)
+        scale = C.apr_conv(la, np.abs(x64), np.abs(w64), tree=tr)
         t = G.fill_tree(acc, xb)
         wd = torch.from_numpy(w32).cuda()
         y32 = G.conv(acc, xb, t, wd, k, out_dtype=torch.float32).cpu().numpy()
@@ -250,7 +253,8 @@ def test_rl_epilogues():
     inp, la, tr = case("sphere64")
     psf = S.gaussian_stencil(5, 1.5)
     wl = G.stencil_levels(psf, "restrict", 5, la.l_min, la.l_max)
-    ref_c = C.apr_conv(la, inp.values.astype(np.float64), wl.astype(np.float64), tree=tr)
+    ref_c = C.apr_conv(la, inp.values.astype(np.float64), S.level_stencils(psf, S.RESTRICT, la.l_min, la.l_max),
+                       tree=tr)
     u = np.random.default_rng(1).uniform(50, 150, la.n).astype(np.float32)
     with G.AprAccess.from_input(inp) as acc:
         x = torch.from_numpy(inp.values).cuda()
