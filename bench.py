@@ -337,6 +337,7 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
     import torch
     from paper_2112_03592_amd import apr as G
     from paper_2112_03592_amd import surrogate as N
+    from aprgen.apr_input import deconv_psf
     edges = SURROGATE_EVAL[which]
     # the FP64 oracle's RL10 of the 256^3 batch APR, stored by
     # tests/golden/make_rl10_deconv256.py (a file, not oracle code)
@@ -372,6 +373,28 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
         rec["error"].append(N.rel_error(res.values, t, ws))
         rec["monitor"].append(res.monitor)
         rec["fallback"].append(bool(res.fallback))
+        if not rec.get("restricted_5cubed"):
+            # the 5^3 convolution with the restricted PSF (every level coarser
+            # than l_max runs the 3^3 neighbourhood) against the same PSF at
+            # every level, on the first APR of the batch
+            tr = G.fill_tree(acc, u)
+            yy = torch.empty_like(u)
+            lv = {}
+            for mode in ("restrict", "same"):
+                wm = torch.from_numpy(G.stencil_levels(deconv_psf(), mode, 5, acc.l_min, acc.l_max)).cuda()
+                G.conv(acc, u, tr, wm, 5, y=yy)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(20):
+                    G.conv(acc, u, tr, wm, 5, y=yy)
+                e1.record()
+                torch.cuda.synchronize()
+                lv[mode + "_ms"] = e0.elapsed_time(e1) / 20
+            lv["edge"] = inp.dims[0]
+            lv["finest_level_share"] = acc.particles_per_level[acc.l_max] / inp.n_particles
+            rec["restricted_5cubed"] = lv
+            del tr, yy
         if gold is not None and inp.dims[0] == int(gold["edge"]) and str(gold["digest"]) == input_digest(inp):
             g = torch.from_numpy(gold["rl10"]).cuda()
             rec["vs_fp64_oracle"] = {"edge": int(gold["edge"]), "n_particles": inp.n_particles,
