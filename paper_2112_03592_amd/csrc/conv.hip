@@ -252,15 +252,20 @@ __device__ __forceinline__ void conv_item(const ConvArgs& a, int l, int tz, int 
     for (int r = 0; r < RPG; ++r) {
       const int s = grp + r * NG;
       const uint32_t e = end[r];
+      // the kinds of row slot r can hold (constants after unrolling: the
+      // code for the others is dropped)
+      const bool r_apr = r * NG < NH, r_tree = r * NG < 2 * NH && (r + 1) * NG > NH;
+      const bool r_coarse = (r + 1) * NG > 2 * NH;
       // element y covers cells [y << sh, ((y + 1) << sh) - 1]
-      const int sh = s < 2 * NH ? 0 : (D == 1 || s < 2 * NH + NCR1 ? 1 : 2);
+      const int sh = !r_coarse || s < 2 * NH ? 0 : (D == 1 || s < 2 * NH + NCR1 ? 1 : 2);
       const bool coarse = sh > 0;
       if (s < NSRC && act[r]) {         // uniform per group
-        const bool istree = s >= NH && !coarse;
+        const bool istree = r_tree && s >= NH && !coarse;
         const uint16_t* __restrict__ ys = istree ? ty : py;
         const TX* __restrict__ vs = istree ? tv : xv;
         const int h = s < NH ? s : s - NH;
-        const bool centre = s < NH && h / HX >= R && h / HX < R + TZ && h % HX >= R && h % HX < R + TXr;
+        const bool centre =
+            r_apr && s < NH && h / HX >= R && h / HX < R + TZ && h % HX >= R && h % HX < R + TXr;
         const int c = (h / HX - R) * TXr + (h % HX - R);
         // coarse row: its element covers 2^sh x 2^sh halo rows from hb (mask
         // of the ones inside the halo and the level-l grid)
@@ -414,7 +419,7 @@ __device__ __forceinline__ void conv_item(const ConvArgs& a, int l, int tz, int 
       // is the row needed by the next window; if so, its first batch
       if (s < NSRC) {
         act[r] = has_next && cur[r] < e && (ny[r] == kUnknown || (ny[r] << sh) <= nwhi);
-        const bool istree = s >= NH && !coarse;
+        const bool istree = r_tree && s >= NH && !coarse;
         const uint16_t* __restrict__ ys = istree ? ty : py;
         const TX* __restrict__ vs = istree ? tv : xv;
         if (act[r]) {
