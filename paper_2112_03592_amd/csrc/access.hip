@@ -4,6 +4,7 @@
 // list of the convolution (the pre-pass of Section 5.2).
 #include <algorithm>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "common.hpp"
@@ -376,6 +377,25 @@ static void free_handle(apr_handle* h) {
 // (finest level first, then z, x) is cut into eight contiguous ranges of equal
 // cost, one per XCD (neighbouring tiles share halo rows in that XCD's L2), and
 // each range runs its heaviest tiles first, so that no long tile starts last.
+// Host threads for the O(N) checks and counts of the build: up to 16, one
+// per 2^20 items.
+static int host_threads(int64_t items) {
+  const int hw = int(std::max(1u, std::thread::hardware_concurrency()));
+  return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(16), int64_t(hw), items >> 20})));
+}
+
+template <typename F>
+static void run_host_threads(int nth, F&& f) {
+  if (nth <= 1) {
+    f(0);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(f, t);
+  f(0);
+  for (auto& th : pool) th.join();
+}
+
 // Work items of the conv launch.  Each tile's y sweep is cut into windows
 // (runs of its output y spanning at most kWinY cells, gaps of at most kWinGap),
 // counted on the host from the LinearAccess.  A work item is a run of one
@@ -393,43 +413,57 @@ static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream
   APR_HIP(hipMemcpyAsync(t.data(), h->tiles, size_t(n) * 8, hipMemcpyDeviceToHost, s));
   APR_HIP(hipStreamSynchronize(s));
   const Meta& m = h->meta;
+  // windows of every tile, tiles split over host threads (each fills its own
+  // lists, concatenated in tile order)
+  const int nth = host_threads(d->n_particles);
+  std::vector<std::vector<uint32_t>> twins(static_cast<size_t>(nth)), tcost(static_cast<size_t>(nth));
+  std::vector<int64_t> nwin(size_t(n), 0);
+  auto tile_windows = [&](int th) {
+    const int64_t i0 = n * th / nth, i1 = n * (th + 1) / nth;
+    std::vector<uint64_t> bits;
+    for (int64_t i = i0; i < i1; ++i) {
+      int l, tz, tx, y0;
+      tile_unpack(t[size_t(i)], l, tz, tx, y0);
+      const int words = (m.dy[l] + 63) / 64;
+      bits.assign(size_t(words), 0);
+      for (int z = tz * kTileZ; z < std::min(m.dz[l], (tz + 1) * kTileZ); ++z)
+        for (int x = tx * kTileX; x < std::min(m.dx[l], (tx + 1) * kTileX); ++x) {
+          const uint64_t row = uint64_t(m.prow[l]) + uint64_t(z) * uint64_t(m.dx[l]) + uint64_t(x);
+          const uint64_t b = row ? d->xz_end[row - 1] : 0, e = d->xz_end[row];
+          for (uint64_t j = b; j < e; ++j) bits[d->y_idx[j] >> 6] |= uint64_t(1) << (d->y_idx[j] & 63);
+        }
+      // first occupied y at or after y (or -1)
+      auto next = [&](int y) {
+        if (y >= m.dy[l]) return -1;
+        for (int w = y >> 6; w < words; ++w) {
+          uint64_t v = bits[size_t(w)];
+          if (w == (y >> 6)) v &= ~uint64_t(0) << (y & 63);
+          if (v) return w * 64 + __builtin_ctzll(v);
+        }
+        return -1;
+      };
+      for (int y = next(0); y >= 0;) {
+        const int w0 = y;
+        int last = y, nx;
+        while ((nx = next(last + 1)) >= 0 && nx - w0 < kWinY && nx - last - 1 <= kWinGap) last = nx;
+        twins[size_t(th)].push_back(uint32_t(w0) | (uint32_t(last) << 16));
+        tcost[size_t(th)].push_back(uint32_t(last - w0 + 1) + 16);
+        ++nwin[size_t(i)];
+        y = nx;
+      }
+    }
+  };
+  run_host_threads(nth, tile_windows);
   std::vector<uint32_t> wins;           // windows, tile by tile in list order
   std::vector<uint32_t> wcost;          // cost of each window: its span + 16 cells
-  std::vector<int64_t> woff(size_t(n) + 1, 0);
-  std::vector<uint64_t> bits;
-  uint64_t total = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    int l, tz, tx, y0;
-    tile_unpack(t[size_t(i)], l, tz, tx, y0);
-    const int words = (m.dy[l] + 63) / 64;
-    bits.assign(size_t(words), 0);
-    for (int z = tz * kTileZ; z < std::min(m.dz[l], (tz + 1) * kTileZ); ++z)
-      for (int x = tx * kTileX; x < std::min(m.dx[l], (tx + 1) * kTileX); ++x) {
-        const uint64_t row = uint64_t(m.prow[l]) + uint64_t(z) * uint64_t(m.dx[l]) + uint64_t(x);
-        const uint64_t b = row ? d->xz_end[row - 1] : 0, e = d->xz_end[row];
-        for (uint64_t j = b; j < e; ++j) bits[d->y_idx[j] >> 6] |= uint64_t(1) << (d->y_idx[j] & 63);
-      }
-    // first occupied y at or after y (or -1)
-    auto next = [&](int y) {
-      if (y >= m.dy[l]) return -1;
-      for (int w = y >> 6; w < words; ++w) {
-        uint64_t v = bits[size_t(w)];
-        if (w == (y >> 6)) v &= ~uint64_t(0) << (y & 63);
-        if (v) return w * 64 + __builtin_ctzll(v);
-      }
-      return -1;
-    };
-    for (int y = next(0); y >= 0;) {
-      const int w0 = y;
-      int last = y, nx;
-      while ((nx = next(last + 1)) >= 0 && nx - w0 < kWinY && nx - last - 1 <= kWinGap) last = nx;
-      wins.push_back(uint32_t(w0) | (uint32_t(last) << 16));
-      wcost.push_back(uint32_t(last - w0 + 1) + 16);
-      total += wcost.back() + kItemCost;
-      y = nx;
-    }
-    woff[size_t(i) + 1] = int64_t(wins.size());
+  for (int th = 0; th < nth; ++th) {
+    wins.insert(wins.end(), twins[size_t(th)].begin(), twins[size_t(th)].end());
+    wcost.insert(wcost.end(), tcost[size_t(th)].begin(), tcost[size_t(th)].end());
   }
+  std::vector<int64_t> woff(size_t(n) + 1, 0);
+  for (int64_t i = 0; i < n; ++i) woff[size_t(i) + 1] = woff[size_t(i)] + nwin[size_t(i)];
+  uint64_t total = 0;
+  for (uint32_t c : wcost) total += c + kItemCost;
   if (wins.size() >= (size_t(1) << 32)) APR_FAIL(APR_EUNSUPPORTED, "apr_access_build: too many sweep windows");
   // items: runs of windows whose cost (item start included) stays within half
   // the ideal share of one of the launch's resident workgroups
@@ -563,31 +597,52 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
   h->n_rows = nrows;
   h->n_trows = ntrows;
   {
-    uint64_t prev = 0;
-    for (int l = d->l_min; l <= lmax; ++l) {
-      const int64_t rows_l = int64_t(m.dz[l]) * m.dx[l];
-      const uint64_t lev_begin = prev;
-      for (int64_t r = 0; r < rows_l; ++r) {
-        const int64_t row = m.prow[l] + r;
+    // rows split over host threads; each chunk starts from the previous
+    // row's end (a chunk whose start is invalid fails at its first row)
+    const int nth = host_threads(nrows);
+    std::vector<int64_t> bad(size_t(nth), -1);
+    std::vector<int> why(size_t(nth), 0);
+    auto check_rows = [&](int t) {
+      const int64_t r0 = nrows * t / nth, r1 = nrows * (t + 1) / nth;
+      int l = d->l_min;
+      uint64_t prev = r0 ? d->xz_end[r0 - 1] : 0;
+      for (int64_t row = r0; row < r1; ++row) {
+        while (l < lmax && row >= int64_t(m.prow[l + 1])) ++l;
         const uint64_t e = d->xz_end[row];
         if (e < prev || e > uint64_t(d->n_particles)) {
-          free_handle(h);
-          APR_FAIL(APR_EINVAL, "apr_access_build: xz_end not monotone or beyond n_particles at row " +
-                                   std::to_string(row));
+          bad[size_t(t)] = row;
+          why[size_t(t)] = 1;
+          return;
         }
-        for (uint64_t i = prev; i < e; ++i) {
-          if (d->y_idx[i] >= m.dy[l] || (i > prev && d->y_idx[i] <= d->y_idx[i - 1])) {
-            free_handle(h);
-            APR_FAIL(APR_EINVAL, "apr_access_build: y_idx out of range or not strictly increasing "
-                                 "in row " + std::to_string(row));
+        for (uint64_t k = prev; k < e; ++k)
+          if (d->y_idx[k] >= m.dy[l] || (k > prev && d->y_idx[k] <= d->y_idx[k - 1])) {
+            bad[size_t(t)] = row;
+            why[size_t(t)] = 2;
+            return;
           }
-        }
         ends[size_t(row)] = uint32_t(e);
         prev = e;
       }
-      h->per_level_p[l] = int64_t(prev - lev_begin);
+    };
+    run_host_threads(nth, check_rows);
+    for (int t = 0; t < nth; ++t) {
+      if (bad[size_t(t)] < 0) continue;
+      free_handle(h);
+      if (why[size_t(t)] == 1)
+        APR_FAIL(APR_EINVAL, "apr_access_build: xz_end not monotone or beyond n_particles at row " +
+                                 std::to_string(bad[size_t(t)]));
+      APR_FAIL(APR_EINVAL, "apr_access_build: y_idx out of range or not strictly increasing in row " +
+                               std::to_string(bad[size_t(t)]));
     }
-    if (prev != uint64_t(d->n_particles)) {
+    for (int l = d->l_min; l <= lmax; ++l) {
+      const int64_t first = m.prow[l], last = first + int64_t(m.dz[l]) * m.dx[l] - 1;
+      h->per_level_p[l] = int64_t(d->xz_end[last]) - (first ? int64_t(d->xz_end[first - 1]) : 0);
+    }
+    if (nrows && d->xz_end[nrows - 1] != uint64_t(d->n_particles)) {
+      free_handle(h);
+      APR_FAIL(APR_EINVAL, "apr_access_build: last xz_end must equal n_particles");
+    }
+    if (!nrows && d->n_particles) {
       free_handle(h);
       APR_FAIL(APR_EINVAL, "apr_access_build: last xz_end must equal n_particles");
     }

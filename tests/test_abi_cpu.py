@@ -102,6 +102,26 @@ def test_build_rejects_malformed_arrays_on_the_host():
     assert st == L.APR_EINVAL
 
 
+def test_build_rejects_malformed_arrays_across_host_threads():
+    """2M rows (one level, one particle per row), checked in chunks by
+    several host threads: the error names the first bad row wherever it
+    falls."""
+    dims, lv = (2048, 1024, 4), 11
+    n = 2048 * 1024
+    y = np.zeros(n, np.uint16)
+    e = np.arange(1, n + 1, dtype=np.uint64)
+    for rows in ([n - 5], [n // 2 + 3, n - 7], [17, n - 1]):
+        yb = y.copy()
+        yb[rows] = 4                       # y beyond the level's y size
+        st, msg = _build_raw(dims, lv, lv, yb, e)
+        assert st == L.APR_EINVAL and f"row {min(rows)}" in msg, msg
+    eb = e.copy()
+    eb[n - 9] = eb[n - 10]                 # an empty row is fine ...
+    eb[n - 9 + 1] = eb[n - 10] - 1         # ... a decreasing end is not
+    st, msg = _build_raw(dims, lv, lv, y[:-1], eb)
+    assert st == L.APR_EINVAL and "not monotone" in msg and f"row {n - 8}" in msg, msg
+
+
 def test_binding_constants_match_the_header():
     """Every #define APR_* the binding names has the header's value."""
     txt = open(HEADER).read()
