@@ -188,7 +188,8 @@ def build_workload(name: str, generator: str):
 def layers_leg(inp, reps: int = 10):
     """The gather path on the same APR: the network layer shapes (1->16,
     16->16 on MFMA with BF16 activations, 16->16 FP32, 16->1), the 16-channel
-    tree fill, and both gradients of a 16->16 layer (FP32)."""
+    tree fill, and both gradients of a 16->16 layer (FP32; the weight
+    gradient also with BF16 activations)."""
     import numpy as np
     import torch
     from aprgen.apr_input import gaussian_stencil
@@ -244,6 +245,7 @@ def layers_leg(inp, reps: int = 10):
     del h16f8, t16f8
     ms["bwd_data_16to16_f32"] = tm(lambda: G.conv_bwd_data(acc, dy, w1616, 3))
     ms["bwd_weight_16to16_f32"] = tm(lambda: G.conv_bwd_weight(acc, h16, t16, dy, 3, nl, 16, 16))
+    ms["bwd_weight_16to16_bf16x"] = tm(lambda: G.conv_bwd_weight(acc, h16b, t16b, dy, 3, nl, 16, 16))
     # MFMA layer against the BF16 matrix peak and the HBM roofline: gathered
     # rows (BF16, 16 channels) of particles and tree, the gather map, outputs
     t = ms["fwd_16to16_bf16_mfma"] * 1e-3

@@ -57,6 +57,7 @@ static apr_status rl_run(const apr_handle* h, int32_t k, int32_t n_wlevels, cons
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t np = h->n_p;
   float* tree = reinterpret_cast<float*>(base);
+  const float* tree_in = h->n_t ? tree : nullptr;   // no tree levels: nothing to read (and rho starts at base)
   float* rho = tree + h->n_t;
   float* ping = rho + np;
   float* pong = ping + np;
@@ -82,7 +83,7 @@ static apr_status rl_run(const apr_handle* h, int32_t k, int32_t n_wlevels, cons
     // rho = u / max(corr(i, w_flip), eps)
     d.epilogue = APR_EPI_RATIO;
     d.epi_arg = u;
-    st = conv_impl(h, &d, cur, tree, w_flip, rho, eps, stream);
+    st = conv_impl(h, &d, cur, tree_in, w_flip, rho, eps, stream);
     if (st != APR_OK) return st;
     st = apr_fill_tree(h, rho, tree, 1, APR_F32, stream);
     if (st != APR_OK) return st;
@@ -90,7 +91,7 @@ static apr_status rl_run(const apr_handle* h, int32_t k, int32_t n_wlevels, cons
     d.epilogue = power == 1.f ? APR_EPI_MUL : APR_EPI_MULPOW;
     d.power = power;
     d.epi_arg = cur;
-    st = conv_impl(h, &d, rho, tree, w, nxt, nullptr, stream);
+    st = conv_impl(h, &d, rho, tree_in, w, nxt, nullptr, stream);
     if (st != APR_OK) return st;
     cur = nxt;
   }

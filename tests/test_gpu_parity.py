@@ -267,6 +267,28 @@ def test_rl_epilogues():
     assert np.allclose(mres, ref_c * u, rtol=2e-5)
 
 
+@pytest.mark.parametrize("name", ["rand33x20x70", "sphere64", "rand_long_y", "single_cell", "one_level",
+                                  "dense13x11x70"])
+def test_richardson_lucy_iterations_equal_the_public_steps(name):
+    """Two Richardson-Lucy iterations equal, bit for bit, the same steps
+    through the public calls (tree fills, the ratio and multiply epilogues),
+    including an APR without tree levels (a single cell)."""
+    inp, la, tr = case(name)
+    psf = S.gaussian_stencil(5, 1.5)
+    u = np.random.default_rng(2).uniform(50, 150, la.n).astype(np.float32)
+    with G.AprAccess.from_input(inp) as acc:
+        ud = torch.from_numpy(u).cuda()
+        got = G.richardson_lucy(acc, ud, psf, 2)
+        w = torch.from_numpy(G.stencil_levels(psf, "restrict", 5, la.l_min, la.l_max)).cuda()
+        wf = torch.from_numpy(G.stencil_levels(psf, "restrict", 5, la.l_min, la.l_max, flip=True)).cuda()
+        eps = float(np.float32(np.abs(u).max()) * np.float32(1e-12))
+        cur = ud
+        for _ in range(2):
+            rho = G.conv(acc, cur, G.fill_tree(acc, cur), wf, 5, epilogue="ratio", epi_arg=ud, eps=eps)
+            cur = G.conv(acc, rho, G.fill_tree(acc, rho), w, 5, epilogue="mul", epi_arg=cur)
+        assert torch.equal(got, cur)
+
+
 def test_validation_rejects_unbalanced_and_broken_partitions():
     from paper_2112_03592_amd._lib import AprError, APR_EUNBALANCED, APR_EPARTITION
     unb = None
