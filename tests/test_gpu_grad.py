@@ -13,7 +13,7 @@ from oracle import conv as C
 from oracle.bf16 import round_bf16, store_mean_bf16
 from oracle.tree import fill_tree as oracle_fill
 from paper_2112_03592_amd import apr as G
-from tests.gpu_common import assert_close_scaled, linear_access
+from tests.gpu_common import SMALL_CASES, assert_close_scaled, linear_access
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +22,12 @@ CASES = {
     "rand9x12x7": lambda: random_apr((9, 12, 7), l_min=1, seed=3, p_refine=0.3),
     "rand33x20x70": lambda: random_apr((33, 20, 70), l_min=2, seed=5, p_refine=0.2),
     "sphere32": lambda: sphere_apr(CONFIGS["sphere32"]),
+    # degenerate structures: one particle and no tree levels; one level
+    # only; every particle at the finest level; levels down to 0
+    "single_cell": SMALL_CASES["single_cell"],
+    "one_level": SMALL_CASES["one_level"],
+    "dense13x11x70": SMALL_CASES["dense13x11x70"],
+    "rand8_l0": SMALL_CASES["rand8_l0"],
 }
 _cache = {}
 
