@@ -217,7 +217,7 @@ typedef struct {
  * level-(l-j) particle lies at least 2^j - 1 level-l cells away).  Stencils
  * above 5^3 (Section 7's extension; single channel, FP32 x and y, any
  * epilogue but APR_EPI_GRADMAG) sum the k^2 lines of the stencil from
- * patches of at most 16 output cells along y.  Single-channel 5^3: a level
+ * patches of at most 32 output cells along y.  Single-channel 5^3: a level
  * whose weights are zero outside the central 3^3 (the restricted stencil of
  * Eq. restrict_stenc at every level coarser than l_max) is evaluated with the
  * 3^3 neighbourhood, taking the same nonzero taps in the same order (equal

@@ -32,9 +32,11 @@ namespace apr {
 
 constexpr int kBig = 1 << 28;    // key of a missing element
 // Launch shape per stencil size: 3^3 in 1024-thread workgroups capped at 64
-// registers (two per CU, eight waves per SIMD), 5^3 in 768-thread workgroups
-// capped at 80 (two per CU, six waves per SIMD; at 64 it spills), larger
-// stencils in 1024-thread workgroups at four waves per SIMD.  Source rows are
+// registers (two per CU, eight waves per SIMD), 5^3 and 7^3 in 768-thread
+// workgroups capped at 80 (two per CU, six waves per SIMD; 5^3 spills at 64,
+// 9^3 at 80), 9^3 to 13^3 in 1024-thread workgroups at four waves per SIMD.
+// Stencils above 5^3 sweep patches of at most 32 output cells (16: 15-34%
+// slower).  Source rows are
 // served by groups of kG lanes; each group moves kG * kNB elements of its row
 // per memory round.  A
 // patch holds output y spans of at most kW cells.  Within radius r of a
@@ -45,11 +47,11 @@ template <int K>
 struct ConvShape {
   static_assert(K % 2 == 1 && K >= 3 && K <= 13, "odd stencil sides 3..13");
   static constexpr bool kLarge = K > 5;
-  static constexpr int kThreads = kLarge || K == 3 ? 1024 : 768;
+  static constexpr int kThreads = (kLarge && K > 7) || K == 3 ? 1024 : 768;
   static constexpr int kG = 8;
   static constexpr int kNB = kLarge ? 1 : 2;
-  static constexpr int kWavesPerSimd = kLarge ? 4 : K == 3 ? 8 : 6;
-  static constexpr int kW = kLarge ? 16 : kWinY;
+  static constexpr int kWavesPerSimd = kLarge && K > 7 ? 4 : K == 3 ? 8 : 6;
+  static constexpr int kW = kLarge ? 32 : kWinY;
   static constexpr int kDepth = kLarge ? 2 : 1;   // coarsest APR source level: l - kDepth
   // patch row stride (floats): the y span plus the halo, padded up to 8 mod 32
   // words up to 5^3, which spreads the rows of a wave's reads and writes over

@@ -144,7 +144,7 @@ def test_conv_fp32(name, k, mode):
 @pytest.mark.parametrize("k", [7, 9, 11, 13])
 @pytest.mark.parametrize("mode", ["restrict", "explicit"])
 def test_conv_large_stencils(name, k, mode):
-    """Stencils above 5^3: taps reach APR level l-2; patches of at most 16
+    """Stencils above 5^3: taps reach APR level l-2; patches of at most 32
     output cells along y."""
     say("conv large", name, k, mode)
     inp, la, tr = case(name)
