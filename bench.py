@@ -339,7 +339,7 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
     import torch
     from paper_2112_03592_amd import apr as G
     from paper_2112_03592_amd import surrogate as N
-    from aprgen.apr_input import deconv_psf
+    from aprgen.apr_input import deconv_psf, gaussian_stencil
     edges = SURROGATE_EVAL[which]
     # the FP64 oracle's RL10 of the 256^3 batch APR, stored by
     # tests/golden/make_rl10_deconv256.py (a file, not oracle code)
@@ -397,6 +397,20 @@ def surrogate_leg(which: str, inputs, reps: int = 3, weights: str = SURROGATE_WE
             lv["finest_level_share"] = acc.particles_per_level[acc.l_max] / inp.n_particles
             rec["restricted_5cubed"] = lv
             del tr, yy
+            # 100 Richardson-Lucy iterations with a 13^3 Gaussian PSF (sigma 2,
+            # restricted per level) on the same 256^3 APR: the size of the
+            # paper's own deconvolution run (Sec. 6.2: 42 s on its CPU, on a
+            # hollow-cylinder image of compression ratio 13.3)
+            psf13 = gaussian_stencil(13, 2.0)
+            G.richardson_lucy(acc, u, psf13, 2)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            G.richardson_lucy(acc, u, psf13, 100)
+            e1.record()
+            torch.cuda.synchronize()
+            rec["rl100_13cubed"] = {"edge": inp.dims[0], "n_particles": inp.n_particles,
+                                    "ms": e0.elapsed_time(e1), "paper_cpu_s": 42.0}
         if gold is not None and inp.dims[0] == int(gold["edge"]) and str(gold["digest"]) == input_digest(inp):
             g = torch.from_numpy(gold["rl10"]).cuda()
             rec["vs_fp64_oracle"] = {"edge": int(gold["edge"]), "n_particles": inp.n_particles,
