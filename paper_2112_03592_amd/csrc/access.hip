@@ -3,6 +3,7 @@
 // device validation of partition and 2:1 balance, and the non-empty tile
 // list of the convolution (the pre-pass of Section 5.2).
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -384,16 +385,30 @@ static int host_threads(int64_t items) {
   return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(16), int64_t(hw), items >> 20})));
 }
 
+// Runs f(0) .. f(nth - 1) on nth threads (the caller's included).  An
+// exception inside a worker (an allocation) is caught there and reported as
+// false, as is a failure to start a worker (f then runs on the caller).
 template <typename F>
-static void run_host_threads(int nth, F&& f) {
-  if (nth <= 1) {
-    f(0);
-    return;
-  }
+static bool run_host_threads(int nth, F&& f) {
+  std::atomic<bool> ok{true};
+  auto guarded = [&](int t) {
+    try {
+      f(t);
+    } catch (...) {
+      ok = false;
+    }
+  };
   std::vector<std::thread> pool;
-  for (int t = 1; t < nth; ++t) pool.emplace_back(f, t);
-  f(0);
+  for (int t = 1; t < nth; ++t) {
+    try {
+      pool.emplace_back(guarded, t);
+    } catch (...) {
+      guarded(t);
+    }
+  }
+  guarded(0);
   for (auto& th : pool) th.join();
+  return ok;
 }
 
 // Work items of the conv launch.  Each tile's y sweep is cut into windows
@@ -453,7 +468,7 @@ static apr_status order_tiles(apr_handle* h, const apr_access_desc* d, hipStream
       }
     }
   };
-  run_host_threads(nth, tile_windows);
+  if (!run_host_threads(nth, tile_windows)) APR_FAIL(APR_ENOMEM, "apr_access_build: out of host memory (tile windows)");
   std::vector<uint32_t> wins;           // windows, tile by tile in list order
   std::vector<uint32_t> wcost;          // cost of each window: its span + 16 cells
   for (int th = 0; th < nth; ++th) {
@@ -624,7 +639,10 @@ static apr_status build_impl(const apr_access_desc* d, hipStream_t s, apr_handle
         prev = e;
       }
     };
-    run_host_threads(nth, check_rows);
+    if (!run_host_threads(nth, check_rows)) {
+      free_handle(h);
+      APR_FAIL(APR_ENOMEM, "apr_access_build: host validation failed to run");
+    }
     for (int t = 0; t < nth; ++t) {
       if (bad[size_t(t)] < 0) continue;
       free_handle(h);
