@@ -16,6 +16,7 @@
 // Every output has a single writer and a fixed summation order: results are
 // deterministic.
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "common.hpp"
@@ -966,47 +967,146 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
 // [l % 16].  Up to 7 FP32 accumulators per lane; the sums go out as FP64
 // partials for the fixed-order reduction.
 // ---------------------------------------------------------------------------
+// Sixteen channels of zeros (FP32 or BF16): the row a padded tap reads.
+__device__ __align__(64) uint32_t kZeroRow[16] = {};
+
+// Byte offsets at and above kBufOob are outside every buffer the BUF form
+// reads (the host takes that form only when x, the tree and one tap's column
+// of the map are smaller), and a raw buffer load outside its buffer's size
+// returns zero.
+constexpr uint32_t kBufOob = 0xF0000000u;
+constexpr int kBufDword3 = 0x00020000;   // buffer resource word 3 on gfx9 parts (raw, 32-bit data)
+
 template <typename TX>
+__device__ inline TX buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, int(off), 0, 0));
+}
+template <>
+__device__ inline __hip_bfloat16 buf_load<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, int(off), 0, 0);
+  return __builtin_bit_cast(__hip_bfloat16, u);
+}
+template <typename TX>
+__device__ inline TX bits_or(TX a, TX b) {
+  using U = typename std::conditional<sizeof(TX) == 4, uint32_t, unsigned short>::type;
+  return __builtin_bit_cast(TX, U(__builtin_bit_cast(U, a) | __builtin_bit_cast(U, b)));
+}
+
+// BUF = true: the gathers are raw buffer loads with 32-bit offsets.  A tap
+// reads both x and the tree, the source it does not use (and a padded tap,
+// both) at an offset past the buffer, which returns zero, so a gather costs a
+// handful of 32-bit operations instead of 64-bit pointer selects; the map
+// columns are buffers too (one per tap, wave-uniform).
+template <typename TX, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void bwd_weight_mfma16_kernel(int64_t p_begin, int64_t p_end,
                                                                 const uint32_t* __restrict__ gmap, int64_t n_p,
                                                                 const TX* __restrict__ x, const TX* __restrict__ tree,
+                                                                uint32_t x_bytes, uint32_t t_bytes,
                                                                 const float* __restrict__ dy,
                                                                 double* __restrict__ partial) {
   constexpr int K3 = 27, NOUT = 16 * 16 * 27, TQ = 7;   // taps per wave: 7, 7, 7, 6
-  const int lane = int(threadIdx.x & 63), wave = int(threadIdx.x >> 6);
+  constexpr int LOGR = sizeof(TX) == 4 ? 6 : 5;         // log2 of the bytes of a 16-channel row
+  const int lane = int(threadIdx.x & 63), wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int r16 = lane & 15, kg = lane >> 4;
   const int q0 = wave * TQ, nq = min(TQ, K3 - q0);
   const int64_t u_b = p_begin + int64_t(blockIdx.x) * kWgtParticles;
   const int64_t u_e = min(p_end, u_b + kWgtParticles);
+  // (unused, and dropped by the compiler, when BUF is false)
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<TX*>(x), 0, int(x_bytes), kBufDword3);
+  const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(const_cast<TX*>(tree), 0, int(t_bytes), kBufDword3);
   mfma_f4 acc[TQ];
 #pragma unroll
   for (int t = 0; t < TQ; ++t) acc[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-  // 32 particles per step: eight groups of four, every gather of the step in flight together
-  constexpr int NJ = 8;
+  // 24 particles per step: six groups of four, every gather of the step in flight together
+  constexpr int NJ = 6, NE = TQ * 4 * NJ, NEP = (NE + 63) / 64;   // map entries of one wave's step
+  // BUF form: the wave's map entries of a step are loaded (coalesced, NEP per
+  // lane, one step ahead) and staged in LDS, then read back as broadcasts,
+  // instead of one load per lane and tap through the texture path.  Entries
+  // past NE are padding that nothing reads.
+  __shared__ uint32_t s_map[4][64 * NEP];
+  uint32_t nxt[NEP];
+  auto load_map = [&](int64_t ps) {
+#pragma unroll
+    for (int r = 0; r < NEP; ++r) {
+      const int i = 64 * r + lane, t = i / (4 * NJ), e = i % (4 * NJ);
+      const int64_t p = ps + e;
+      nxt[r] = gmap[size_t(min(q0 + t, K3 - 1)) * size_t(n_p) + size_t(p < u_e ? p : u_b)];
+    }
+  };
+  if constexpr (BUF) load_map(u_b);
   for (int64_t p0 = u_b; p0 < u_e; p0 += 4 * NJ) {
     float a[NJ];
     uint32_t g[NJ][TQ];
+    if constexpr (BUF) {
+      __builtin_amdgcn_wave_barrier();   // the previous step's reads of s_map come first
+#pragma unroll
+      for (int r = 0; r < NEP; ++r)   // entries of particles past the block's end read as padded
+        s_map[wave][64 * r + lane] = p0 + (64 * r + lane) % (4 * NJ) < u_e ? nxt[r] : kPad;
+      __builtin_amdgcn_wave_barrier();
+      load_map(p0 + 4 * NJ);
+    }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int64_t p = p0 + 4 * j + kg;
       const bool valid = p < u_e;
-      a[j] = valid ? dy[size_t(p) * 16 + r16] : 0.f;
+      const size_t pc = size_t(valid ? p : u_b);   // loads stay unconditional (u_b < u_e)
+      a[j] = dy[pc * 16 + r16];   // zero past the block's end: masked at the product
+      // the last wave's seventh tap (past 27) re-reads tap 26 into an
+      // accumulator that is never stored
 #pragma unroll
-      for (int t = 0; t < TQ; ++t)
-        g[j][t] = (valid && t < nq) ? gmap[size_t(q0 + t) * size_t(n_p) + size_t(p)] : kPad;
+      for (int t = 0; t < TQ; ++t) {
+        if constexpr (BUF) {
+          g[j][t] = s_map[wave][t * 4 * NJ + 4 * j + kg];
+        } else {
+          const uint32_t gv = gmap[size_t(min(q0 + t, K3 - 1)) * size_t(n_p) + pc];
+          g[j][t] = valid ? gv : kPad;
+        }
+      }
     }
-    float b[NJ][TQ];
+    // Every gather is issued unconditionally, a padded tap reading zeros, and
+    // all of them before the first product, so the loads stay in flight
+    // together (no branch and no wait per tap).  The scheduling barriers keep
+    // the compiler from pulling a use up to its load.
+    TX raw[NJ][TQ];
+    if constexpr (BUF) {
+      __builtin_amdgcn_sched_barrier(0);
+      TX vt[NJ][TQ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int t = 0; t < TQ; ++t)
-        b[j][t] = (g[j][t] != kPad)
-                      ? to_f32<TX>((((g[j][t] >> 30) == 3) ? tree : x)[size_t(g[j][t] & kIdxMask) * 16 + r16])
-                      : 0.f;
+        for (int t = 0; t < TQ; ++t) {
+          // a padded tap (all ones) is a tree tap whose row is clamped past the
+          // end; a particle past the block's end reads as padded
+          const uint32_t gg = g[j][t];
+          const bool in_tree = gg >= 0xC0000000u;
+          const uint32_t off = (min(gg & kIdxMask, kBufOob >> LOGR) << LOGR) | uint32_t(r16 * int(sizeof(TX)));
+          raw[j][t] = buf_load<TX>(rx, in_tree ? kBufOob : off);
+          vt[j][t] = buf_load<TX>(rt, in_tree ? off : kBufOob);
+        }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int t = 0; t < TQ; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j][t], acc[t], 0, 0, 0);
+        for (int t = 0; t < TQ; ++t) raw[j][t] = bits_or(raw[j][t], vt[j][t]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int t = 0; t < TQ; ++t) {
+          const uint32_t gg = g[j][t];
+          const TX* src = gg == kPad ? reinterpret_cast<const TX*>(kZeroRow) : ((gg >> 30) == 3 ? tree : x);
+          raw[j][t] = src[size_t(gg == kPad ? 0u : (gg & kIdxMask)) * 16 + r16];
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const float aj = p0 + 4 * j + kg < u_e ? a[j] : 0.f;
+#pragma unroll
+      for (int t = 0; t < TQ; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aj, to_f32<TX>(raw[j][t]), acc[t], 0, 0, 0);
+    }
   }
   double* out = partial + size_t(blockIdx.x) * NOUT;
 #pragma unroll
@@ -1015,6 +1115,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 #pragma unroll
     for (int i = 0; i < 4; ++i) out[((4 * kg + i) * 16 + r16) * K3 + q0 + t] = double(acc[t][i]);
   }
+}
+
+// APR_WIDE_OFFSETS=1 in the environment selects the 64-bit addressing form of
+// the 16 -> 16 weight gradient at every size (it is otherwise taken only above
+// the buffer limit), so that both forms can be compared on small inputs.
+static bool wide_offsets_forced() {
+  const char* e = std::getenv("APR_WIDE_OFFSETS");
+  return e && e[0] && e[0] != '0';
 }
 
 template <int K, int CI, int CO, typename TX>
@@ -1028,11 +1136,16 @@ static apr_status bwd_weight_impl(const apr_handle* h, const apr_conv_desc* d, c
     const int nb = level_blocks(h, l);
     if (!nb) continue;
     const int64_t b = level_first(h, l);
-    if constexpr (kMfma)
-      hipLaunchKernelGGL((bwd_weight_mfma16_kernel<TX>), dim3(nb), dim3(256), 0, s, b, b + h->per_level_p[l],
+    if constexpr (kMfma) {
+      // 32-bit buffer offsets when x, the tree and a map column stay below kBufOob bytes
+      const uint64_t xb = uint64_t(h->n_p) * 16 * sizeof(TX), tb = uint64_t(h->n_t) * 16 * sizeof(TX);
+      const bool buf = xb <= kBufOob && tb <= kBufOob && uint64_t(h->n_p) * 4 <= kBufOob && !wide_offsets_forced();
+      auto kern = buf ? bwd_weight_mfma16_kernel<TX, true> : bwd_weight_mfma16_kernel<TX, false>;
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, b, b + h->per_level_p[l],
                          reinterpret_cast<const uint32_t*>(gather_map(h, K)), h->n_p, static_cast<const TX*>(x),
-                         static_cast<const TX*>(tree), dy, ws + size_t(blk) * NOUT);
-    else
+                         static_cast<const TX*>(h->n_t ? tree : nullptr), uint32_t(buf ? xb : 0),
+                         uint32_t(buf ? tb : 0), dy, ws + size_t(blk) * NOUT);
+    } else
       hipLaunchKernelGGL((bwd_weight_partial_kernel<K, CI, CO, TX>), dim3(nb), dim3(kWgtThreads), 0, s, b,
                          b + h->per_level_p[l], gather_map(h, K), h->n_p, static_cast<const TX*>(x),
                          static_cast<const TX*>(tree), dy, ws + size_t(blk) * NOUT);

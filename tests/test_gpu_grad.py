@@ -133,6 +133,39 @@ def test_backward_weight_bf16_x(name, cin, cout):
     assert_close_scaled(dw, ref, sc, 1e-5, f"dW BF16 x {name} {cin}->{cout}")
 
 
+@pytest.mark.parametrize("name", ["rand33x20x70", "sphere32", "dense13x11x70"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_backward_weight_16_both_address_forms(name, dtype, monkeypatch):
+    """The 16 -> 16 weight gradient reads its gathers through 32-bit buffer
+    offsets up to a size limit and through 64-bit addresses above it;
+    APR_WIDE_OFFSETS=1 forces the second form here.  Both sum the same
+    products in the same order, so they agree bit for bit, and with the
+    oracle."""
+    say("bwd weight address forms", name, dtype)
+    inp, la, tr, W, _ = _setup(name, 3, 16, 16, seed=60)
+    rng = np.random.default_rng(61)
+    # BF16-exact values in [1, 4): the BF16 tree means are exact (as in the
+    # BF16 test above), so the oracle's fill matches the stored tree
+    x = round_bf16(rng.uniform(1.0, 4.0, size=(la.n, 16))).astype(np.float32)
+    g = rng.normal(size=(la.n, 16)).astype(np.float32)
+    with G.AprAccess.from_input(inp, gather=(3,)) as acc:
+        xd = torch.from_numpy(x).cuda()
+        if dtype == "bf16":
+            xd = xd.to(torch.bfloat16)
+        t = G.fill_tree(acc, xd)
+        gd = torch.from_numpy(g).cuda()
+        dw_buf = G.conv_bwd_weight(acc, xd, t, gd, 3, W.shape[0], 16, 16).cpu().numpy()
+        monkeypatch.setenv("APR_WIDE_OFFSETS", "1")
+        dw_wide = G.conv_bwd_weight(acc, xd, t, gd, 3, W.shape[0], 16, 16).cpu().numpy()
+        monkeypatch.delenv("APR_WIDE_OFFSETS")
+    assert np.array_equal(dw_buf, dw_wide)
+    x64, g64 = x.astype(np.float64), g.astype(np.float64)
+    tv = oracle_fill(la, tr, x64, store=store_mean_bf16) if dtype == "bf16" else None
+    ref = C.apr_conv_bwd_weight(la, x64, g64, 3, n_wlevels=W.shape[0], tree=tr, tvals=tv)
+    sc = C.apr_conv_bwd_weight(la, x64, np.abs(g64), 3, n_wlevels=W.shape[0], tree=tr, tvals=tv)
+    assert_close_scaled(dw_buf, ref, sc, 1e-5, f"dW 16->16 {dtype} {name}")
+
+
 @pytest.mark.parametrize("k,cin,cout", [(3, 16, 16), (5, 1, 1), (3, 1, 16)])
 def test_adjoint_identity_on_device(k, cin, cout):
     """<A v, g> from the device forward equals <v, A^T g> from the device
