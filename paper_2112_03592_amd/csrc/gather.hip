@@ -472,6 +472,45 @@ static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const 
   }
 }
 
+// APR_WIDE_OFFSETS=1 in the environment selects the 64-bit addressing forms of
+// the 16 -> 16 weight gradient and data-gradient kernels at every size (they
+// are otherwise taken only above the buffer limit), so that both forms can be
+// compared on small inputs.
+static bool wide_offsets_forced() {
+  const char* e = std::getenv("APR_WIDE_OFFSETS");
+  return e && e[0] && e[0] != '0';
+}
+
+// Sixteen channels of zeros (FP32 or BF16): the row a padded tap reads.
+__device__ __align__(64) uint32_t kZeroRow[16] = {};
+
+// Byte offsets at and above kBufOob are outside every buffer the BUF form
+// reads (the host takes that form only when x, the tree and one tap's column
+// of the map are smaller), and a raw buffer load outside its buffer's size
+// returns zero.
+constexpr uint32_t kBufOob = 0xF0000000u;
+constexpr int kBufDword3 = 0x00020000;   // buffer resource word 3 on gfx9 parts (raw, 32-bit data)
+
+template <typename TX>
+__device__ inline TX buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, int(off), 0, 0));
+}
+template <>
+__device__ inline __hip_bfloat16 buf_load<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, int(off), 0, 0);
+  return __builtin_bit_cast(__hip_bfloat16, u);
+}
+__device__ inline mfma_f4 buf_load_row4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(mfma_f4, __builtin_amdgcn_raw_buffer_load_b128(r, int(off), 0, 0));
+}
+template <typename TX>
+__device__ inline TX bits_or(TX a, TX b) {
+  using U = typename std::conditional<sizeof(TX) == 4, uint32_t, unsigned short>::type;
+  return __builtin_bit_cast(TX, U(__builtin_bit_cast(U, a) | __builtin_bit_cast(U, b)));
+}
+
 // ---------------------------------------------------------------------------
 // 16 -> 16 channels with FP32 rows on MFMA (v_mfma_f32_16x16x4_f32), for the
 // FP32 forward and for the same-level part of the data gradient (BWD: rows
@@ -483,12 +522,14 @@ static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const 
 // lane layout as in the BF16 kernel.  B operands staged per block in LDS in
 // lane order; persistent waves over an XCD-contiguous tile range.
 // ---------------------------------------------------------------------------
-template <bool BWD, typename TY>
+template <bool BWD, typename TY, bool BUF>
 __global__ __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(1, 4))) void mc16_f32_mfma_kernel(
     const uint32_t* __restrict__ gmap, int64_t n_p, uint32_t p_begin, uint32_t p_end, const float* __restrict__ rows,
-    const float* __restrict__ tree, const float* __restrict__ w_level, const float* __restrict__ bias, int relu,
-    const TY* __restrict__ residual, TY* __restrict__ out) {
+    uint32_t rows_bytes, const float* __restrict__ tree, const float* __restrict__ w_level,
+    const float* __restrict__ bias, int relu, const TY* __restrict__ residual, TY* __restrict__ out) {
   constexpr int K3 = 27;
+  // (unused, and dropped by the compiler, when BUF is false)
+  const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(rows), 0, int(rows_bytes), kBufDword3);
   __shared__ mfma_f4 sb[K3][64];
   for (int j = threadIdx.x; j < K3 * 64; j += 64 * kMfmaWaves) {
     const int q = j / 64, ln = j % 64, n = ln & 15, k = ln >> 4;
@@ -516,19 +557,30 @@ __global__ __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu
     const bool valid = p < p_end;
     uint32_t g[K3];
 #pragma unroll
-    for (int q = 0; q < K3; ++q) {
-      g[q] = valid ? gmap[size_t(BWD ? K3 - 1 - q : q) * size_t(n_p) + p] : kPad;
-      if (BWD && g[q] != kPad && (g[q] >> 30) != 1) g[q] = kPad;
+    for (int q = 0; q < K3; ++q) {   // unconditional loads (a row past the end reads the first)
+      const uint32_t gv = gmap[size_t(BWD ? K3 - 1 - q : q) * size_t(n_p) + (valid ? p : p_begin)];
+      g[q] = valid ? gv : kPad;
     }
-    // every gathered row of the tile in flight before the first product
+    // every gathered row of the tile in flight before the first product, no
+    // branch per tap: a padded tap (in the adjoint, every tap whose source is
+    // not a same-level particle) reads zeros
     mfma_f4 a[K3];
 #pragma unroll
     for (int q = 0; q < K3; ++q) {
-      a[q] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-      if (g[q] != kPad)
-        a[q] = *reinterpret_cast<const mfma_f4*>(((!BWD && (g[q] >> 30) == 3) ? tree : rows) +
-                                                 size_t(g[q] & kIdxMask) * 16 + 4 * kg);
+      const uint32_t gg = g[q];
+      if constexpr (BWD) {
+        const bool use = (gg >> 30) == 1;
+        if constexpr (BUF)
+          a[q] = buf_load_row4(rr, use ? ((gg & kIdxMask) << 6) | uint32_t(kg << 4) : kBufOob);
+        else
+          a[q] = *reinterpret_cast<const mfma_f4*>((use ? rows : reinterpret_cast<const float*>(kZeroRow)) +
+                                                   size_t(use ? gg & kIdxMask : 0u) * 16 + 4 * kg);
+      } else {
+        const float* src = gg == kPad ? reinterpret_cast<const float*>(kZeroRow) : ((gg >> 30) == 3 ? tree : rows);
+        a[q] = *reinterpret_cast<const mfma_f4*>(src + size_t(gg == kPad ? 0u : gg & kIdxMask) * 16 + 4 * kg);
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
     mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < K3; ++q) {
@@ -554,9 +606,13 @@ static void launch_mc16_f32_mfma(const apr_handle* h, uint32_t begin, uint32_t n
                                  TY* out, hipStream_t s) {
   const uint32_t tiles = (np_l + 15) / 16;
   const uint32_t blocks_per_xcd = std::min<uint32_t>(kMfmaBlocksPerXcd, (tiles / 8 + kMfmaWaves) / kMfmaWaves);
-  hipLaunchKernelGGL((mc16_f32_mfma_kernel<BWD, TY>), dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)),
-                     dim3(64 * kMfmaWaves), 0, s, reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p, begin,
-                     begin + np_l, rows, tree, wl, bias, relu, residual, out);
+  // the adjoint reads dY rows through 32-bit buffer offsets below kBufOob bytes
+  const uint64_t rb = uint64_t(h->n_p) * 64;
+  const bool buf = BWD && rb <= kBufOob && !wide_offsets_forced();
+  auto kern = buf ? mc16_f32_mfma_kernel<BWD, TY, true> : mc16_f32_mfma_kernel<BWD, TY, false>;
+  hipLaunchKernelGGL(kern, dim3(8 * std::max<uint32_t>(1, blocks_per_xcd)), dim3(64 * kMfmaWaves), 0, s,
+                     reinterpret_cast<const uint32_t*>(gather_map(h, 3)), h->n_p, begin, begin + np_l, rows,
+                     uint32_t(buf ? rb : 0), tree, wl, bias, relu, residual, out);
 }
 
 template <int K, int CI, int CO, typename TX, typename TY>
@@ -967,33 +1023,6 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
 // [l % 16].  Up to 7 FP32 accumulators per lane; the sums go out as FP64
 // partials for the fixed-order reduction.
 // ---------------------------------------------------------------------------
-// Sixteen channels of zeros (FP32 or BF16): the row a padded tap reads.
-__device__ __align__(64) uint32_t kZeroRow[16] = {};
-
-// Byte offsets at and above kBufOob are outside every buffer the BUF form
-// reads (the host takes that form only when x, the tree and one tap's column
-// of the map are smaller), and a raw buffer load outside its buffer's size
-// returns zero.
-constexpr uint32_t kBufOob = 0xF0000000u;
-constexpr int kBufDword3 = 0x00020000;   // buffer resource word 3 on gfx9 parts (raw, 32-bit data)
-
-template <typename TX>
-__device__ inline TX buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <>
-__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, int(off), 0, 0));
-}
-template <>
-__device__ inline __hip_bfloat16 buf_load<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, int(off), 0, 0);
-  return __builtin_bit_cast(__hip_bfloat16, u);
-}
-template <typename TX>
-__device__ inline TX bits_or(TX a, TX b) {
-  using U = typename std::conditional<sizeof(TX) == 4, uint32_t, unsigned short>::type;
-  return __builtin_bit_cast(TX, U(__builtin_bit_cast(U, a) | __builtin_bit_cast(U, b)));
-}
-
 // BUF = true: the gathers are raw buffer loads with 32-bit offsets.  A tap
 // reads both x and the tree, the source it does not use (and a padded tap,
 // both) at an offset past the buffer, which returns zero, so a gather costs a
@@ -1115,14 +1144,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 #pragma unroll
     for (int i = 0; i < 4; ++i) out[((4 * kg + i) * 16 + r16) * K3 + q0 + t] = double(acc[t][i]);
   }
-}
-
-// APR_WIDE_OFFSETS=1 in the environment selects the 64-bit addressing form of
-// the 16 -> 16 weight gradient at every size (it is otherwise taken only above
-// the buffer limit), so that both forms can be compared on small inputs.
-static bool wide_offsets_forced() {
-  const char* e = std::getenv("APR_WIDE_OFFSETS");
-  return e && e[0] && e[0] != '0';
 }
 
 template <int K, int CI, int CO, typename TX>

@@ -135,11 +135,11 @@ def test_backward_weight_bf16_x(name, cin, cout):
 
 @pytest.mark.parametrize("name", ["rand33x20x70", "sphere32", "dense13x11x70"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_backward_weight_16_both_address_forms(name, dtype, monkeypatch):
-    """The 16 -> 16 weight gradient reads its gathers through 32-bit buffer
-    offsets up to a size limit and through 64-bit addresses above it;
-    APR_WIDE_OFFSETS=1 forces the second form here.  Both sum the same
-    products in the same order, so they agree bit for bit, and with the
+def test_backward_16_both_address_forms(name, dtype, monkeypatch):
+    """The 16 -> 16 weight and data gradients read their gathers through
+    32-bit buffer offsets up to a size limit and through 64-bit addresses
+    above it; APR_WIDE_OFFSETS=1 forces the second form here.  Both sum the
+    same products in the same order, so they agree bit for bit, and with the
     oracle."""
     say("bwd weight address forms", name, dtype)
     inp, la, tr, W, _ = _setup(name, 3, 16, 16, seed=60)
@@ -154,16 +154,24 @@ def test_backward_weight_16_both_address_forms(name, dtype, monkeypatch):
             xd = xd.to(torch.bfloat16)
         t = G.fill_tree(acc, xd)
         gd = torch.from_numpy(g).cuda()
+        wd = torch.from_numpy(W).cuda()
         dw_buf = G.conv_bwd_weight(acc, xd, t, gd, 3, W.shape[0], 16, 16).cpu().numpy()
+        dx_buf = G.conv_bwd_data(acc, gd, wd, 3).cpu().numpy()
         monkeypatch.setenv("APR_WIDE_OFFSETS", "1")
         dw_wide = G.conv_bwd_weight(acc, xd, t, gd, 3, W.shape[0], 16, 16).cpu().numpy()
+        dx_wide = G.conv_bwd_data(acc, gd, wd, 3).cpu().numpy()
         monkeypatch.delenv("APR_WIDE_OFFSETS")
     assert np.array_equal(dw_buf, dw_wide)
+    assert np.array_equal(dx_buf, dx_wide)
     x64, g64 = x.astype(np.float64), g.astype(np.float64)
     tv = oracle_fill(la, tr, x64, store=store_mean_bf16) if dtype == "bf16" else None
     ref = C.apr_conv_bwd_weight(la, x64, g64, 3, n_wlevels=W.shape[0], tree=tr, tvals=tv)
     sc = C.apr_conv_bwd_weight(la, x64, np.abs(g64), 3, n_wlevels=W.shape[0], tree=tr, tvals=tv)
     assert_close_scaled(dw_buf, ref, sc, 1e-5, f"dW 16->16 {dtype} {name}")
+    W64 = W.astype(np.float64)
+    ref_dx = C.apr_conv_bwd_data(la, g64, W64, tree=tr)
+    sc_dx = C.apr_conv_bwd_data(la, np.abs(g64), np.abs(W64), tree=tr)
+    assert_close_scaled(dx_buf, ref_dx, sc_dx, 1e-5, f"dX 16->16 {name}")
 
 
 @pytest.mark.parametrize("k,cin,cout", [(3, 16, 16), (5, 1, 1), (3, 1, 16)])
