@@ -258,7 +258,12 @@ size_t apr_conv_bwd_weight_ws(const apr_handle* h, const apr_conv_desc* d);
  * (summed over levels when d->n_wlevels == 1).  x, tree: as in apr_conv
  * (tree filled from x); dy: FP32 [N_p][c_out]; dw: FP32 (overwritten); ws:
  * device workspace of apr_conv_bwd_weight_ws bytes.  FP32 block sums, FP64
- * partials reduced in a fixed order: deterministic.  Asynchronous. */
+ * partials reduced in a fixed order: deterministic.  Asynchronous.
+ * The 16 -> 16, k = 3 kernels of both gradients address their gathers with
+ * 32-bit buffer offsets while the gathered arrays (x and the tree here, dy in
+ * apr_conv_bwd_data) stay below 0xF0000000 bytes, and with 64-bit addresses
+ * above; the environment variable APR_WIDE_OFFSETS=1 selects the second form
+ * at every size (both give the same bits; it exists for testing). */
 apr_status apr_conv_bwd_weight(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                                const float* dy, float* dw, void* ws, size_t ws_bytes, void* stream);
 

@@ -484,10 +484,9 @@ static bool wide_offsets_forced() {
 // Sixteen channels of zeros (FP32 or BF16): the row a padded tap reads.
 __device__ __align__(64) uint32_t kZeroRow[16] = {};
 
-// Byte offsets at and above kBufOob are outside every buffer the BUF form
-// reads (the host takes that form only when x, the tree and one tap's column
-// of the map are smaller), and a raw buffer load outside its buffer's size
-// returns zero.
+// Byte offsets at and above kBufOob are outside every buffer the BUF forms
+// read (the host takes those forms only when the gathered arrays are
+// smaller), and a raw buffer load outside its buffer's size returns zero.
 constexpr uint32_t kBufOob = 0xF0000000u;
 constexpr int kBufDword3 = 0x00020000;   // buffer resource word 3 on gfx9 parts (raw, 32-bit data)
 
@@ -1027,7 +1026,7 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
 // reads both x and the tree, the source it does not use (and a padded tap,
 // both) at an offset past the buffer, which returns zero, so a gather costs a
 // handful of 32-bit operations instead of 64-bit pointer selects; the map
-// columns are buffers too (one per tap, wave-uniform).
+// entries of a step come through LDS.
 template <typename TX, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void bwd_weight_mfma16_kernel(int64_t p_begin, int64_t p_end,
                                                                 const uint32_t* __restrict__ gmap, int64_t n_p,
@@ -1158,9 +1157,9 @@ static apr_status bwd_weight_impl(const apr_handle* h, const apr_conv_desc* d, c
     if (!nb) continue;
     const int64_t b = level_first(h, l);
     if constexpr (kMfma) {
-      // 32-bit buffer offsets when x, the tree and a map column stay below kBufOob bytes
+      // 32-bit buffer offsets when x and the tree stay below kBufOob bytes
       const uint64_t xb = uint64_t(h->n_p) * 16 * sizeof(TX), tb = uint64_t(h->n_t) * 16 * sizeof(TX);
-      const bool buf = xb <= kBufOob && tb <= kBufOob && uint64_t(h->n_p) * 4 <= kBufOob && !wide_offsets_forced();
+      const bool buf = xb <= kBufOob && tb <= kBufOob && !wide_offsets_forced();
       auto kern = buf ? bwd_weight_mfma16_kernel<TX, true> : bwd_weight_mfma16_kernel<TX, false>;
       hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, b, b + h->per_level_p[l],
                          reinterpret_cast<const uint32_t*>(gather_map(h, K)), h->n_p, static_cast<const TX*>(x),
