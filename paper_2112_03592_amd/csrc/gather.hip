@@ -843,13 +843,15 @@ __device__ inline void acc_inverse(const uint32_t* __restrict__ inv_ent, uint32_
     for (int co = 0; co < COUT; ++co) g[co] = 0.f;
     bool any = false;
     while (i < e && int(c % K3) == q) {
+      // the next entry is read before this row (unconditionally: e - 1 is an entry of this source)
+      const uint32_t cn = inv_ent[min(i + 1, e - 1)];
       float v[COUT];
       load_vec<float, COUT>(dy + size_t(c / K3) * COUT, v);
 #pragma unroll
       for (int co = 0; co < COUT; ++co) g[co] += v[co];
       any = true;
       ++i;
-      c = i < e ? inv_ent[i] : 0xffffffffu;
+      c = i < e ? cn : 0xffffffffu;
     }
     if (!__any(any)) continue;
     const float* w = sw + q * COUT * CIN;
