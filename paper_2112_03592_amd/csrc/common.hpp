@@ -14,6 +14,9 @@ namespace apr {
 
 constexpr int kMaxL = APR_MAX_LEVELS;
 constexpr uint32_t kNoY = 0x7fffffffu;   // "no further element" marker for y searches
+// child-map entry of a child cell outside the image; else (1 << 31 if a tree
+// node) | index
+constexpr uint32_t kChildPad = 0xffffffffu;
 
 // Per-level geometry, passed by value to kernels.
 struct Meta {
@@ -175,7 +178,7 @@ struct apr_handle {
   int64_t n_items = 0;
   int64_t xcd_off[9] = {0};   // items of XCD x: [xcd_off[x], xcd_off[x + 1]), heaviest first
   int32_t* gmap[2] = {nullptr, nullptr};   // gather maps for k = 3, 5: [k^3][n_p]
-  uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t]
+  uint32_t* cmap = nullptr;                 // child map of the tree nodes [8][n_t] (kChildPad outside the image)
   // inverse of the gather maps for the coarse and tree taps: for source s
   // (particle s as a coarser source, or tree node t at n_p + t) the readers
   // p * k^3 + q with gmap[q][p] naming s, sorted, at inv_ent[inv_off[s] ..

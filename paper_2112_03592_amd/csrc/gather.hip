@@ -152,6 +152,38 @@ __global__ __launch_bounds__(64 * kGWaves) void push_down_kernel(
   }
 }
 
+// The same step parent-major, on the child map: one lane per tree node of
+// level P adds its gradient divided by its child count to each child (tree
+// nodes and particles of level P + 1).  Every child has one parent, so no two
+// lanes write one row, and each child gets the same single addition as above.
+template <int CIN>
+__global__ __launch_bounds__(256) void push_down_parent_kernel(const uint32_t* __restrict__ cmap, int64_t n_t,
+                                                               uint32_t t_begin, uint32_t t_end,
+                                                               float* __restrict__ dt, float* __restrict__ dx) {
+  const uint32_t i = t_begin + blockIdx.x * 256u + threadIdx.x;
+  if (i >= t_end) return;
+  uint32_t code[8];
+  int n = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    code[j] = cmap[size_t(j) * size_t(n_t) + i];
+    n += code[j] != kChildPad;
+  }
+  const float inv = 1.f / float(n);
+  float v[CIN];
+  load_vec<float, CIN>(dt + size_t(i) * CIN, v);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (code[j] == kChildPad) continue;
+    float* o = ((code[j] >> 31) ? dt : dx) + size_t(code[j] & 0x7fffffffu) * CIN;
+    float u[CIN];
+    load_vec<float, CIN>(o, u);
+#pragma unroll
+    for (int c = 0; c < CIN; ++c) u[c] += v[c] * inv;
+    store_vec<float, CIN>(o, u);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Weight gradient: block j of level l sums dY[p, co] * Xcat[src(p, o), ci]
 // over its particles (staged PCH at a time in LDS) for every (co, ci, o), in
@@ -998,16 +1030,27 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
     tb += nt_l;
   }
   // adjoint of the child means, coarsest tree level first
-  for (int L = m.t_lo + 1; L <= m.t_hi; ++L) {
-    const int64_t rows = int64_t(m.dz[L]) * m.dx[L];
-    hipLaunchKernelGGL((push_down_kernel<CI>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
-                       dim3(64 * kGWaves), 0, s, m, L, h->ty, h->tend, m.trow[L], h->ty, h->tend, dt, dt);
-  }
-  for (int l = std::max(m.l_min, m.t_lo + 1); l <= m.l_max; ++l) {
-    if (!h->per_level_p[l]) continue;
-    const int64_t rows = int64_t(m.dz[l]) * m.dx[l];
-    hipLaunchKernelGGL((push_down_kernel<CI>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
-                       dim3(64 * kGWaves), 0, s, m, l, h->py, h->pend, m.prow[l], h->ty, h->tend, dt, dx);
+  if (h->cmap) {
+    uint32_t pb = 0;
+    for (int P = m.t_lo; P <= m.t_hi; ++P) {
+      const uint32_t np_ = uint32_t(h->per_level_t[P]);
+      if (np_)
+        hipLaunchKernelGGL((push_down_parent_kernel<CI>), dim3((np_ + 255) / 256), dim3(256), 0, s, h->cmap, h->n_t,
+                           pb, pb + np_, dt, dx);
+      pb += np_;
+    }
+  } else {
+    for (int L = m.t_lo + 1; L <= m.t_hi; ++L) {
+      const int64_t rows = int64_t(m.dz[L]) * m.dx[L];
+      hipLaunchKernelGGL((push_down_kernel<CI>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
+                         dim3(64 * kGWaves), 0, s, m, L, h->ty, h->tend, m.trow[L], h->ty, h->tend, dt, dt);
+    }
+    for (int l = std::max(m.l_min, m.t_lo + 1); l <= m.l_max; ++l) {
+      if (!h->per_level_p[l]) continue;
+      const int64_t rows = int64_t(m.dz[l]) * m.dx[l];
+      hipLaunchKernelGGL((push_down_kernel<CI>), dim3(unsigned((rows + kGWaves - 1) / kGWaves)),
+                         dim3(64 * kGWaves), 0, s, m, l, h->py, h->pend, m.prow[l], h->ty, h->tend, dt, dx);
+    }
   }
   APR_HIP(hipGetLastError());
   return APR_OK;

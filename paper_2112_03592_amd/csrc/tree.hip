@@ -19,8 +19,6 @@ namespace apr {
 constexpr int kFillWaves = 4;
 constexpr int kWin = 64;   // parent cells per window
 
-constexpr uint32_t kChildPad = 0xffffffffu;   // child-map entry of a child cell outside the image
-
 // INDEX: write child codes ((1 << 31 if tree node) | index) to cmap [8][n_t]
 // instead of the means
 template <typename T, bool INDEX>
