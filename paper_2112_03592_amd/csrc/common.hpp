@@ -185,6 +185,10 @@ struct apr_handle {
   // inv_off[s + 1])
   uint32_t* inv_off[2] = {nullptr, nullptr};
   uint32_t* inv_ent[2] = {nullptr, nullptr};
+  // particles that have readers in the inverse map, ascending (so level by
+  // level): level l's are inv_act[inv_act_lvl[l] .. inv_act_lvl[l + 1])
+  uint32_t* inv_act[2] = {nullptr, nullptr};
+  int64_t inv_act_lvl[2][apr::kMaxL + 2] = {};
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
 };

@@ -896,9 +896,12 @@ __device__ inline void acc_inverse(const uint32_t* __restrict__ inv_ent, uint32_
 
 // SAME = false: only the readers from the inverse map, added to dx (the
 // same-level part was written by the MFMA kernel)
+// act (SAME = false only): the lanes take the particles act[p_begin ..
+// p_end) instead of p_begin .. p_end - 1
 template <int K, int CIN, int COUT, bool SAME>
 __global__ __launch_bounds__(kInvThreads) void bwd_dx_kernel(const uint32_t* __restrict__ gmap, int64_t n_p,
                                                              uint32_t p_begin, uint32_t p_end,
+                                                             const uint32_t* __restrict__ act,
                                                              const uint32_t* __restrict__ inv_off,
                                                              const uint32_t* __restrict__ inv_ent,
                                                              const float* __restrict__ dy, const float* w_l,
@@ -908,8 +911,9 @@ __global__ __launch_bounds__(kInvThreads) void bwd_dx_kernel(const uint32_t* __r
   if (SAME) stage_wt<K, CIN, COUT>(w_l, sw);
   if (w_fine) stage_wt<K, CIN, COUT>(w_fine, swf);
   __syncthreads();
-  const uint32_t s = p_begin + blockIdx.x * uint32_t(kInvThreads) + threadIdx.x;
-  if (s >= p_end) return;
+  const uint32_t j = p_begin + blockIdx.x * uint32_t(kInvThreads) + threadIdx.x;
+  if (j >= p_end) return;
+  const uint32_t s = (!SAME && act) ? act[j] : j;
   if (!SAME && !(w_fine && inv_off[s + 1] > inv_off[s])) return;
   float acc[CIN];
   if (SAME) {
@@ -951,6 +955,19 @@ __global__ __launch_bounds__(kInvThreads) void bwd_dt_kernel(int64_t n_p, uint32
   store_vec<float, CIN>(dt + size_t(t) * CIN, acc);
 }
 
+// particles s with readers in the inverse map: flag, then (after an exclusive
+// scan of the flags) scatter s to its rank
+__global__ void inv_act_flag_kernel(const uint32_t* __restrict__ off, int64_t n_p, uint32_t* __restrict__ flag) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s < n_p) flag[s] = off[s + 1] > off[s] ? 1u : 0u;
+}
+
+__global__ void inv_act_scatter_kernel(const uint32_t* __restrict__ off, int64_t n_p,
+                                       const uint32_t* __restrict__ rank, uint32_t* __restrict__ act) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s < n_p && off[s + 1] > off[s]) act[rank[s]] = uint32_t(s);
+}
+
 apr_status build_inverse_map(apr_handle* h, int k, hipStream_t s,
                              apr_status (*alloc_u32)(apr_handle*, uint32_t**, int64_t),
                              apr_status (*scan)(uint32_t*, int64_t, uint32_t*, hipStream_t), uint32_t* total_dev) {
@@ -988,6 +1005,36 @@ apr_status build_inverse_map(apr_handle* h, int k, hipStream_t s,
                      h->inv_ent[gi]);
   hipLaunchKernelGGL(inv_sort_kernel, dim3(gt), dim3(256), 0, s, h->inv_off[gi], n_targets, k3, h->inv_ent[gi]);
   APR_HIP(hipGetLastError());
+  // the particles with readers, compacted (the cursor array is reused for the
+  // flags and their exclusive scan), and where each level's run starts
+  const unsigned gpn = unsigned((h->n_p + 255) / 256);
+  hipLaunchKernelGGL(inv_act_flag_kernel, dim3(gpn), dim3(256), 0, s, h->inv_off[gi], h->n_p, cursor);
+  APR_HIP(hipGetLastError());
+  st = scan(cursor, h->n_p, total_dev, s);
+  if (st != APR_OK) {
+    (void)hipFree(cursor);
+    return st;
+  }
+  uint32_t n_act = 0;
+  APR_HIP(hipMemcpyAsync(&n_act, total_dev, 4, hipMemcpyDeviceToHost, s));
+  APR_HIP(hipStreamSynchronize(s));
+  st = alloc_u32(h, &h->inv_act[gi], std::max<int64_t>(n_act, 1));
+  if (st != APR_OK) {
+    (void)hipFree(cursor);
+    return st;
+  }
+  hipLaunchKernelGGL(inv_act_scatter_kernel, dim3(gpn), dim3(256), 0, s, h->inv_off[gi], h->n_p, cursor,
+                     h->inv_act[gi]);
+  APR_HIP(hipGetLastError());
+  const Meta& m = h->meta;
+  int64_t first = 0;
+  for (int l = m.l_min; l <= m.l_max + 1; ++l) {
+    uint32_t r = n_act;
+    if (first < h->n_p) APR_HIP(hipMemcpyAsync(&r, cursor + first, 4, hipMemcpyDeviceToHost, s));
+    APR_HIP(hipStreamSynchronize(s));
+    h->inv_act_lvl[gi][l] = r;
+    if (l <= m.l_max) first += h->per_level_p[l];
+  }
   APR_HIP(hipStreamSynchronize(s));
   (void)hipFree(cursor);
   return APR_OK;
@@ -1008,14 +1055,16 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
     if (np_l) {
       if constexpr (K == 3 && CI == 16 && CO == 16) {
         launch_mc16_f32_mfma<true, float>(h, begin, np_l, dy, nullptr, wlev(l), nullptr, 0, nullptr, dx, s);
-        if (wf)
-          hipLaunchKernelGGL((bwd_dx_kernel<K, CI, CO, false>), dim3((np_l + kInvThreads - 1) / kInvThreads),
-                             dim3(kInvThreads), 0, s, gm, h->n_p, begin, begin + np_l, h->inv_off[gi], h->inv_ent[gi],
-                             dy, wlev(l), wf, dx);
+        // only the level's particles that have readers at level l + 1
+        const uint32_t ab = uint32_t(h->inv_act_lvl[gi][l]), ae = uint32_t(h->inv_act_lvl[gi][l + 1]);
+        if (wf && ae > ab)
+          hipLaunchKernelGGL((bwd_dx_kernel<K, CI, CO, false>), dim3((ae - ab + kInvThreads - 1) / kInvThreads),
+                             dim3(kInvThreads), 0, s, gm, h->n_p, ab, ae, h->inv_act[gi], h->inv_off[gi],
+                             h->inv_ent[gi], dy, wlev(l), wf, dx);
       } else {
         hipLaunchKernelGGL((bwd_dx_kernel<K, CI, CO, true>), dim3((np_l + kInvThreads - 1) / kInvThreads),
-                           dim3(kInvThreads), 0, s, gm, h->n_p, begin, begin + np_l, h->inv_off[gi], h->inv_ent[gi],
-                           dy, wlev(l), wf, dx);
+                           dim3(kInvThreads), 0, s, gm, h->n_p, begin, begin + np_l, nullptr, h->inv_off[gi],
+                           h->inv_ent[gi], dy, wlev(l), wf, dx);
       }
     }
     begin += np_l;
