@@ -263,7 +263,9 @@ size_t apr_conv_bwd_weight_ws(const apr_handle* h, const apr_conv_desc* d);
  * 32-bit buffer offsets while the gathered arrays (x and the tree here, dy in
  * apr_conv_bwd_data) stay below 0xF0000000 bytes, and with 64-bit addresses
  * above; the environment variable APR_WIDE_OFFSETS=1 selects the second form
- * at every size (both give the same bits; it exists for testing). */
+ * at every size, and =2 the weight gradient's two-buffer form that it takes
+ * when x and the tree lie too far apart for one buffer (all forms give the
+ * same bits; the variable exists for testing). */
 apr_status apr_conv_bwd_weight(const apr_handle* h, const apr_conv_desc* d, const void* x, const void* tree,
                                const float* dy, float* dw, void* ws, size_t ws_bytes, void* stream);
 

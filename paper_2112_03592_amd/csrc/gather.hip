@@ -508,10 +508,12 @@ static void launch_mc16_mfma(const apr_handle* h, const apr_conv_desc* d, const 
 // the 16 -> 16 weight gradient and data-gradient kernels at every size (they
 // are otherwise taken only above the buffer limit), so that both forms can be
 // compared on small inputs.
-static bool wide_offsets_forced() {
+// (APR_WIDE_OFFSETS=2: the weight gradient's two-buffer 32-bit form instead.)
+static int wide_offsets_mode() {
   const char* e = std::getenv("APR_WIDE_OFFSETS");
-  return e && e[0] && e[0] != '0';
+  return (e && e[0] == '2') ? 2 : (e && e[0] && e[0] != '0') ? 1 : 0;
 }
+static bool wide_offsets_forced() { return wide_offsets_mode() == 1; }
 
 // Sixteen channels of zeros (FP32 or BF16): the row a padded tap reads.
 __device__ __align__(64) uint32_t kZeroRow[16] = {};
@@ -1121,13 +1123,20 @@ static apr_status bwd_data_impl(const apr_handle* h, const apr_conv_desc* d, con
 // both) at an offset past the buffer, which returns zero, so a gather costs a
 // handful of 32-bit operations instead of 64-bit pointer selects; the map
 // entries of a step come through LDS.
-template <typename TX, bool BUF>
+//
+// MODE 0: 64-bit addresses; 1: x and the tree as two buffers (above);
+// 2: x and the tree lie within kBufOob bytes of each other, and one buffer
+// spanning both (based at x, which then is the lower of the two; x_off and
+// t_off their byte offsets in it) serves every gather with one load.
+template <typename TX, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void bwd_weight_mfma16_kernel(int64_t p_begin, int64_t p_end,
                                                                 const uint32_t* __restrict__ gmap, int64_t n_p,
                                                                 const TX* __restrict__ x, const TX* __restrict__ tree,
                                                                 uint32_t x_bytes, uint32_t t_bytes,
+                                                                uint32_t x_off, uint32_t t_off,
                                                                 const float* __restrict__ dy,
                                                                 double* __restrict__ partial) {
+  constexpr bool BUF = MODE != 0;
   constexpr int K3 = 27, NOUT = 16 * 16 * 27, TQ = 7;   // taps per wave: 7, 7, 7, 6
   constexpr int LOGR = sizeof(TX) == 4 ? 6 : 5;         // log2 of the bytes of a 16-channel row
   const int lane = int(threadIdx.x & 63), wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -1192,7 +1201,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     // together (no branch and no wait per tap).  The scheduling barriers keep
     // the compiler from pulling a use up to its load.
     TX raw[NJ][TQ];
-    if constexpr (BUF) {
+    if constexpr (MODE == 2) {
+      __builtin_amdgcn_sched_barrier(0);
+      const uint32_t xo = x_off + uint32_t(r16 * int(sizeof(TX))), to = t_off + uint32_t(r16 * int(sizeof(TX)));
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int t = 0; t < TQ; ++t) {
+          const uint32_t gg = g[j][t];
+          const uint32_t off = ((gg & kIdxMask) << LOGR) + (gg >= 0xC0000000u ? to : xo);
+          raw[j][t] = buf_load<TX>(rx, gg == kPad ? kBufOob : off);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    } else if constexpr (BUF) {
       __builtin_amdgcn_sched_barrier(0);
       TX vt[NJ][TQ];
 #pragma unroll
@@ -1251,14 +1272,30 @@ static apr_status bwd_weight_impl(const apr_handle* h, const apr_conv_desc* d, c
     if (!nb) continue;
     const int64_t b = level_first(h, l);
     if constexpr (kMfma) {
-      // 32-bit buffer offsets when x and the tree stay below kBufOob bytes
+      // 32-bit buffer offsets when x and the tree stay below kBufOob bytes:
+      // one buffer over both when they lie close enough, else one each
       const uint64_t xb = uint64_t(h->n_p) * 16 * sizeof(TX), tb = uint64_t(h->n_t) * 16 * sizeof(TX);
-      const bool buf = xb <= kBufOob && tb <= kBufOob && !wide_offsets_forced();
-      auto kern = buf ? bwd_weight_mfma16_kernel<TX, true> : bwd_weight_mfma16_kernel<TX, false>;
+      const int forced = wide_offsets_mode();
+      const uintptr_t xa = reinterpret_cast<uintptr_t>(x), ta = reinterpret_cast<uintptr_t>(tree);
+      const uintptr_t lo = (h->n_t && ta < xa) ? ta : xa;
+      const uintptr_t hi = std::max<uintptr_t>(xa + xb, h->n_t ? ta + tb : 0);
+      int mode = xb <= kBufOob && tb <= kBufOob && forced != 1 ? 1 : 0;
+      if (mode == 1 && forced == 0 && hi - lo <= kBufOob) mode = 2;
+      const TX* xp = static_cast<const TX*>(x);
+      const TX* tp = static_cast<const TX*>(h->n_t ? tree : nullptr);
+      uint32_t xbytes = uint32_t(mode ? xb : 0), tbytes = uint32_t(mode ? tb : 0), xoff = 0, toff = 0;
+      if (mode == 2) {
+        xp = reinterpret_cast<const TX*>(lo);
+        xbytes = uint32_t(hi - lo);
+        xoff = uint32_t(xa - lo);
+        toff = h->n_t ? uint32_t(ta - lo) : 0u;
+      }
+      auto kern = mode == 2   ? bwd_weight_mfma16_kernel<TX, 2>
+                  : mode == 1 ? bwd_weight_mfma16_kernel<TX, 1>
+                              : bwd_weight_mfma16_kernel<TX, 0>;
       hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, b, b + h->per_level_p[l],
-                         reinterpret_cast<const uint32_t*>(gather_map(h, K)), h->n_p, static_cast<const TX*>(x),
-                         static_cast<const TX*>(h->n_t ? tree : nullptr), uint32_t(buf ? xb : 0),
-                         uint32_t(buf ? tb : 0), dy, ws + size_t(blk) * NOUT);
+                         reinterpret_cast<const uint32_t*>(gather_map(h, K)), h->n_p, xp, tp, xbytes, tbytes, xoff,
+                         toff, dy, ws + size_t(blk) * NOUT);
     } else
       hipLaunchKernelGGL((bwd_weight_partial_kernel<K, CI, CO, TX>), dim3(nb), dim3(kWgtThreads), 0, s, b,
                          b + h->per_level_p[l], gather_map(h, K), h->n_p, static_cast<const TX*>(x),

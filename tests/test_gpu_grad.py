@@ -138,9 +138,10 @@ def test_backward_weight_bf16_x(name, cin, cout):
 def test_backward_16_both_address_forms(name, dtype, monkeypatch):
     """The 16 -> 16 weight and data gradients read their gathers through
     32-bit buffer offsets up to a size limit and through 64-bit addresses
-    above it; APR_WIDE_OFFSETS=1 forces the second form here.  Both sum the
-    same products in the same order, so they agree bit for bit, and with the
-    oracle."""
+    above it; APR_WIDE_OFFSETS=1 forces the second form here, and =2 the
+    weight gradient's two-buffer form (x and the tree too far apart for one
+    buffer).  All sum the same products in the same order, so they agree bit
+    for bit, and with the oracle."""
     say("bwd weight address forms", name, dtype)
     inp, la, tr, W, _ = _setup(name, 3, 16, 16, seed=60)
     rng = np.random.default_rng(61)
@@ -160,8 +161,11 @@ def test_backward_16_both_address_forms(name, dtype, monkeypatch):
         monkeypatch.setenv("APR_WIDE_OFFSETS", "1")
         dw_wide = G.conv_bwd_weight(acc, xd, t, gd, 3, W.shape[0], 16, 16).cpu().numpy()
         dx_wide = G.conv_bwd_data(acc, gd, wd, 3).cpu().numpy()
+        monkeypatch.setenv("APR_WIDE_OFFSETS", "2")   # x and the tree as two buffers
+        dw_two = G.conv_bwd_weight(acc, xd, t, gd, 3, W.shape[0], 16, 16).cpu().numpy()
         monkeypatch.delenv("APR_WIDE_OFFSETS")
     assert np.array_equal(dw_buf, dw_wide)
+    assert np.array_equal(dw_buf, dw_two)
     assert np.array_equal(dx_buf, dx_wide)
     x64, g64 = x.astype(np.float64), g.astype(np.float64)
     tv = oracle_fill(la, tr, x64, store=store_mean_bf16) if dtype == "bf16" else None
