@@ -2,7 +2,8 @@
 against the workspace entry point (apr_richardson_lucy) on the same inputs:
 two calls in a row on the shared static scratch, the second on a smaller
 APR, each equal to the workspace result; a handle beyond the scratch's size
-is rejected without a launch."""
+is rejected without a launch; the entry point captured in a HIP graph
+replays to the eager result."""
 import sys
 
 import numpy as np
@@ -66,3 +67,42 @@ def test_static_rl_rejects_a_handle_beyond_the_scratch():
         assert e.value.status == L.APR_EINVAL and "static scratch" in str(e.value)
         torch.cuda.synchronize()
         assert float(out.abs().max()) == 0.0                    # nothing was launched
+
+
+def test_static_rl_replayed_from_a_captured_graph():
+    """The allocation-free entry point captured in a HIP graph (its launches
+    are kernel nodes only): three replays, with eager calls and
+    synchronisations between them, each equal bit for bit to the eager result."""
+    psf = deconv_psf()
+    k = psf.shape[-1]
+    inp = sphere_apr(deconv_config(64, 8302))
+    acc = G.AprAccess.from_input(inp)
+    u = torch.from_numpy(np.maximum(inp.values, 0).astype(np.float32)).cuda()
+    w = torch.from_numpy(G.stencil_levels(psf, "restrict", k, acc.l_min, acc.l_max)).cuda()
+    wf = torch.from_numpy(G.stencil_levels(psf, "restrict", k, acc.l_min, acc.l_max, flip=True)).cuda()
+    out = torch.empty_like(u)
+    say("static RL graph capture, 64^3", acc.n_particles)
+    G.richardson_lucy_static(acc, u, w, wf, 10, out=out)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        G.richardson_lucy_static(acc, u, w, wf, 10, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        G.richardson_lucy_static(acc, u, w, wf, 10, out=out)
+    torch.cuda.synchronize()
+    scratch = torch.empty_like(u)
+    for r in range(3):
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {r}"
+        G.richardson_lucy_static(acc, u, w, wf, 3, out=scratch)   # eager work between replays
+        torch.cuda.synchronize()
+    del g
+    acc.close()
