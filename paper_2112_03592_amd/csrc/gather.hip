@@ -1173,8 +1173,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     if constexpr (BUF) {
       __builtin_amdgcn_wave_barrier();   // the previous step's reads of s_map come first
 #pragma unroll
-      for (int r = 0; r < NEP; ++r)   // entries of particles past the block's end read as padded
-        s_map[wave][64 * r + lane] = p0 + (64 * r + lane) % (4 * NJ) < u_e ? nxt[r] : kPad;
+      for (int r = 0; r < NEP; ++r) {   // entries of particles past the block's end read as padded
+        const uint32_t gg = p0 + (64 * r + lane) % (4 * NJ) < u_e ? nxt[r] : kPad;
+        if constexpr (MODE == 2) {
+          // staged as the row's byte offset in the span buffer (past it when
+          // padded; the shift drops the source bits), so a gather adds only
+          // its lane's channel offset
+          s_map[wave][64 * r + lane] =
+              gg == kPad ? kBufOob : (gg << LOGR) + (gg >= 0xC0000000u ? t_off : x_off);
+        } else {
+          s_map[wave][64 * r + lane] = gg;
+        }
+      }
       __builtin_amdgcn_wave_barrier();
       load_map(p0 + 4 * NJ);
     }
@@ -1203,15 +1213,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     TX raw[NJ][TQ];
     if constexpr (MODE == 2) {
       __builtin_amdgcn_sched_barrier(0);
-      const uint32_t xo = x_off + uint32_t(r16 * int(sizeof(TX))), to = t_off + uint32_t(r16 * int(sizeof(TX)));
+      const uint32_t lo_ch = uint32_t(r16 * int(sizeof(TX)));
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
 #pragma unroll
-        for (int t = 0; t < TQ; ++t) {
-          const uint32_t gg = g[j][t];
-          const uint32_t off = ((gg & kIdxMask) << LOGR) + (gg >= 0xC0000000u ? to : xo);
-          raw[j][t] = buf_load<TX>(rx, gg == kPad ? kBufOob : off);
-        }
+        for (int t = 0; t < TQ; ++t) raw[j][t] = buf_load<TX>(rx, g[j][t] + lo_ch);
       __builtin_amdgcn_sched_barrier(0);
     } else if constexpr (BUF) {
       __builtin_amdgcn_sched_barrier(0);
