@@ -219,11 +219,9 @@ def layers_leg(inp, reps: int = 10):
     bias16, bias1 = rnd(16), rnd(1)
     x1 = device_values(inp).view(-1, 1)
     t1 = G.fill_tree(acc, x1)
-    # each tree allocated right after its values: the weight gradient then
-    # reads both through one buffer (they lie within 3.75 GB of each other)
     h16 = rnd(n_p, 16)
-    t16 = G.fill_tree(acc, h16)
     h16b = h16.to(torch.bfloat16)
+    t16 = G.fill_tree(acc, h16)
     t16b = G.fill_tree(acc, h16b)
     dy = rnd(n_p, 16)
     rec = {"n_particles": n_p, "ms": {}}

@@ -1157,6 +1157,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   // instead of one load per lane and tap through the texture path.  Entries
   // past NE are padding that nothing reads.
   __shared__ uint32_t s_map[4][64 * NEP];
+  __shared__ uint2 s_off2[MODE == 1 ? 4 : 1][MODE == 1 ? 64 * NEP : 1];   // two-buffer form: (x, tree) offsets
   uint32_t nxt[NEP];
   auto load_map = [&](int64_t ps) {
 #pragma unroll
@@ -1181,6 +1182,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
           // its lane's channel offset
           s_map[wave][64 * r + lane] =
               gg == kPad ? kBufOob : (gg << LOGR) + (gg >= 0xC0000000u ? t_off : x_off);
+        } else if constexpr (MODE == 1) {
+          // the offsets in x and in the tree, the unused one (both when
+          // padded) past its buffer
+          const bool in_tree = gg >= 0xC0000000u, pad = gg == kPad;
+          const uint32_t off = gg << LOGR;
+          s_off2[wave][64 * r + lane] = make_uint2(in_tree ? kBufOob : off, (in_tree && !pad) ? off : kBufOob);
         } else {
           s_map[wave][64 * r + lane] = gg;
         }
@@ -1198,8 +1205,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
       // accumulator that is never stored
 #pragma unroll
       for (int t = 0; t < TQ; ++t) {
-        if constexpr (BUF) {
+        if constexpr (MODE == 2) {
           g[j][t] = s_map[wave][t * 4 * NJ + 4 * j + kg];
+        } else if constexpr (MODE == 1) {
+          g[j][t] = 0u;   // (the offsets are read at the gathers)
         } else {
           const uint32_t gv = gmap[size_t(min(q0 + t, K3 - 1)) * size_t(n_p) + pc];
           g[j][t] = valid ? gv : kPad;
@@ -1221,18 +1230,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
       __builtin_amdgcn_sched_barrier(0);
     } else if constexpr (BUF) {
       __builtin_amdgcn_sched_barrier(0);
+      const uint32_t lo_ch = uint32_t(r16 * int(sizeof(TX)));
       TX vt[NJ][TQ];
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int t = 0; t < TQ; ++t) {
-          // a padded tap (all ones) is a tree tap whose row is clamped past the
-          // end; a particle past the block's end reads as padded
-          const uint32_t gg = g[j][t];
-          const bool in_tree = gg >= 0xC0000000u;
-          const uint32_t off = (min(gg & kIdxMask, kBufOob >> LOGR) << LOGR) | uint32_t(r16 * int(sizeof(TX)));
-          raw[j][t] = buf_load<TX>(rx, in_tree ? kBufOob : off);
-          vt[j][t] = buf_load<TX>(rt, in_tree ? off : kBufOob);
+          const uint2 o = s_off2[wave][t * 4 * NJ + 4 * j + kg];
+          raw[j][t] = buf_load<TX>(rx, o.x + lo_ch);
+          vt[j][t] = buf_load<TX>(rt, o.y + lo_ch);
         }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
