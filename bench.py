@@ -505,6 +505,8 @@ def main():
     ap.add_argument("--surrogate-weights", default=SURROGATE_WEIGHTS, help="trained surrogate (.npz)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate comparison and print its record (profiling)")
+    ap.add_argument("--layers-only", action="store_true",
+                    help="run only the gather-path layer timings and print their record (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -530,7 +532,7 @@ def main():
 
     # CPU work that uses worker processes runs before the GPU is touched
     sur_inputs = None
-    if args.surrogate_eval != "none" and os.path.exists(args.surrogate_weights):
+    if args.surrogate_eval != "none" and os.path.exists(args.surrogate_weights) and not args.layers_only:
         sur_inputs = surrogate_inputs(args.surrogate_eval)
     if args.surrogate_only:
         print(json.dumps(surrogate_leg(args.surrogate_eval, sur_inputs, weights=args.surrogate_weights)
@@ -540,6 +542,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.layers_only:
+        print(json.dumps(layers_leg(build_workload(args.layers_workload, args.generator))), flush=True)
+        return
 
     log(f"workload {args.workload}: building the APR ({args.generator} generator)")
     t0 = time.perf_counter()
